@@ -1,0 +1,223 @@
+/*
+ * inplace_merge.h -- C ABI of the MI355X (gfx950) parallel in-place merge.
+ *
+ * Method: Bramas & Bramas, "On the improvement of the in-place merge algorithm
+ * parallelization" (arXiv 2005.12648).  Two sorted runs A|B that sit next to
+ * each other in one buffer (Sec. 1, problem statement) are split into
+ * independent pairs A_0 B_0 A_1 B_1 ... (Sec. 3, the division of A B into
+ * pairs), the pairs are made contiguous by in-place partition exchanges
+ * (Sec. 3.4, linear shifting), level by level as in the recursive strategy of
+ * Alg. 3 (sRecPar), and each pair is merged independently (Alg. 2/3, the
+ * per-pair merge).
+ *
+ * Conventions that hold for every entry point:
+ *  - Pointers named d_* or documented as "device" are device pointers on the
+ *    current HIP device.  The caller owns them; the library never frees or
+ *    retains them after the call returns.
+ *  - Work is enqueued on `stream` and is asynchronous: a return value of 0
+ *    means "validated and enqueued", not "finished".  Kernel faults surface at
+ *    the caller's next synchronisation.  A NULL stream means the default
+ *    stream.
+ *  - The result is the STABLE merge: equal keys keep A before B and keep their
+ *    order inside a run (the paper does not discuss ties; this is the reading
+ *    of the per-pair std::inplace_merge, which is stable).
+ *  - Inputs must be two ascending runs.  This is not checked unless the
+ *    environment variable IM_CHECK=1 is set (then the call synchronises the
+ *    stream and returns IM_ERR_NOT_SORTED on unsorted input).  Unsorted input
+ *    without checking yields an unspecified permutation of the input but never
+ *    an access outside [data, data + L_A + L_B).
+ *  - Return value: IM_OK (0) or a negative IM_ERR_* code.  Nothing throws
+ *    across this boundary.  inplace_merge_last_error() returns a thread-local
+ *    description of the last failure on the calling thread.
+ *  - Concurrent calls on different streams of the same device share the
+ *    library's workspace only through a per-device lock: they are safe but
+ *    serialised at enqueue time; the enqueued work itself may overlap only if
+ *    the caller supplies a private workspace per stream (see
+ *    inplace_merge_set_workspace).
+ */
+#ifndef INPLACE_MERGE_H
+#define INPLACE_MERGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Key / payload element types. Keys are compared as the named integer type. */
+typedef enum {
+    IM_INT32 = 0,
+    IM_UINT32 = 1,
+    IM_INT64 = 2,
+    IM_UINT64 = 3
+} im_dtype;
+
+/* Status codes. */
+enum {
+    IM_OK = 0,
+    IM_ERR_INVALID_ARG = -1,       /* NULL pointer, negative length, ...      */
+    IM_ERR_UNSUPPORTED_DTYPE = -2, /* dtype outside im_dtype                  */
+    IM_ERR_HIP = -3,               /* a HIP runtime call failed               */
+    IM_ERR_WORKSPACE = -4,         /* workspace too small / allocation failed */
+    IM_ERR_NOT_SORTED = -5,        /* IM_CHECK=1 and an input run is unsorted */
+    IM_ERR_UNIMPLEMENTED = -6,
+    IM_ERR_DEVICE = -7             /* a device-side bounded wait gave up      */
+};
+
+/* Statistics of the most recent merge enqueued by the calling thread.
+ * Fields filled from device counters are only valid after the stream has
+ * been synchronised and inplace_merge_fetch_stats() has been called. */
+typedef struct {
+    int64_t leaf_capacity;   /* largest pair merged without further division */
+    int64_t tile;            /* elements per workgroup in the pair merge      */
+    int32_t max_levels;      /* division levels enqueued                      */
+    int32_t levels_used;     /* division levels that had work (device)        */
+    int64_t leaves;          /* pairs merged (device)                         */
+    int64_t tiles;           /* workgroup tiles in the pair merge (device)    */
+    int64_t rotations;       /* partition exchanges performed (device)        */
+    int64_t rotated_elems;   /* elements moved by partition exchanges (dev.)  */
+    int64_t search_probes;   /* key-pair probes in all split searches (dev.)  */
+    int64_t searches;        /* split searches performed (device)             */
+} im_stats;
+
+/* ---------------------------------------------------------------------- */
+/* Plain in-place merge (Sec. 1 problem; Sec. 3 division; Alg. 3 levels;  */
+/* Sec. 3.4 linear shifting; per-pair merge of Alg. 2/3).                 */
+/* ---------------------------------------------------------------------- */
+
+/* Merge data[0, L_A) and data[L_A, L_A+L_B) in place (device buffer of
+ * L_A+L_B elements of type `dtype`).  Early exits (Alg. 1 first lines and
+ * the entry test of Alg. 2/3): nothing happens when L_A == 0, L_B == 0 or
+ * A[last] <= B[0]; when A[0] > B[last] a single exchange B|A is done. */
+int inplace_merge(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream);
+
+/* Key + payload variant (structure of arrays): keys[] and vals[] have
+ * L_A+L_B elements each; only keys are compared, every move carries the
+ * payload.  val_dtype: any im_dtype (only its size, 4 or 8 bytes, matters). */
+int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B,
+                     int key_dtype, int val_dtype, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched segmented merge: n independent instances in one buffer.         */
+/* ---------------------------------------------------------------------- */
+
+/* d_offsets: device int64[2n+1], non-decreasing.  Instance q has
+ *   A = data[d_offsets[2q],   d_offsets[2q+1])
+ *   B = data[d_offsets[2q+1], d_offsets[2q+2]).
+ * total_elems: an upper bound of d_offsets[2n] (sizes the workspace).
+ * max_instance: an upper bound of the largest instance (A+B) or 0 if unknown
+ * (then total_elems is used); it sets how many division levels are enqueued.
+ * Offsets are validated on the device only when IM_CHECK=1. */
+int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n,
+                          int64_t total_elems, int64_t max_instance,
+                          int dtype, hipStream_t stream);
+
+int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
+                             int64_t total_elems, int64_t max_instance,
+                             int key_dtype, int val_dtype, hipStream_t stream);
+
+/* In-place merge sort of data[0, n): each tile is sorted in LDS, then
+ * bottom-up passes of the batched merge double the sorted run length; the
+ * unpaired last run of a pass is carried over unchanged. */
+int inplace_merge_sort(void *data, int64_t n, int dtype, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Workspace, errors, statistics.                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace a merge of `total_elems` elements in `n_inst`
+ * instances needs (the library allocates it lazily per device if none is
+ * set).  The workspace holds split descriptors and counters only: its size
+ * grows with the number of workgroup tiles, never with the data itself. */
+size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dtype);
+
+/* Use caller-owned device memory as the workspace of the current device
+ * (NULL/0 returns to library-owned workspace).  The caller keeps ownership
+ * and must keep it alive while enqueued work uses it. */
+int inplace_merge_set_workspace(void *d_ws, size_t bytes);
+
+const char *inplace_merge_last_error(void);
+
+/* Copy the statistics of the last enqueued merge of this thread into *out.
+ * Synchronises `stream` to read the device counters. */
+int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Stage entry points (used by the unit parity tests and the benchmark).   */
+/* ---------------------------------------------------------------------- */
+
+/* Co-rank (Sec. 3.1, the exact "optimal" split for any output rank): for
+ * each diagonal d_k[p] in [0, L_A+L_B], d_out[p] = number of A elements among
+ * the first d_k[p] outputs of the stable merge of data[0,L_A) and
+ * data[L_A,L_A+L_B).  One wavefront lane per diagonal.  All device pointers. */
+int im_corank(const void *data, int64_t L_A, int64_t L_B, int dtype,
+              const int64_t *d_k, int64_t nk, int64_t *d_out, hipStream_t stream);
+
+/* Partition exchange (Sec. 3.4): data[0, lx+ly) = X|Y becomes Y|X.  Equal
+ * sizes use one block swap (one linear-shifting step); otherwise the
+ * exchange is done by three reversals on the device. elem_bytes: 4 or 8. */
+int im_rotate(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Learned split: a 1->H->1 ReLU network (H = 32, fp32) predicts co-ranks;  */
+/* an exponential-then-binary search always corrects the prediction to the */
+/* exact co-rank, so results are identical to inplace_merge().              */
+/* Not part of the paper.                                                   */
+/* ---------------------------------------------------------------------- */
+typedef struct merge_model merge_model;
+
+#define IM_MLP_HIDDEN 32
+#define IM_MLP_PARAMS (3 * IM_MLP_HIDDEN + 1)   /* w1[H], b1[H], w2[H], b2 */
+
+typedef struct {
+    int64_t samples;    /* diagonals sampled for training labels (>= 2)  */
+    int32_t steps;      /* optimiser steps                               */
+    float lr;           /* Adam learning rate                            */
+    uint64_t seed;      /* initialisation seed                           */
+} merge_train_cfg;
+
+/* Create a model from host parameters (IM_MLP_PARAMS floats) or, if
+ * params == NULL, from a deterministic seeded initialisation. */
+int merge_model_create(merge_model **m, const float *params, uint64_t seed);
+
+/* Train on the GPU: labels are produced by the plain co-rank search at
+ * `samples` evenly spaced diagonals of the given runs, then `steps` Adam
+ * steps run with the library's forward/backward/update kernels.
+ * Synchronises `stream` at the end (the model lives on the device). */
+int merge_model_train(merge_model *m, const void *data, int64_t L_A, int64_t L_B,
+                      int dtype, const merge_train_cfg *cfg, hipStream_t stream);
+
+/* One forward+backward pass of the mean squared error on device samples
+ * d_x[M], d_t[M] (fp32) with the model's current parameters; writes the
+ * gradient (IM_MLP_PARAMS floats) to d_grad and the loss to d_loss. */
+int merge_model_grad(const merge_model *m, const float *d_x, const float *d_t, int64_t M,
+                     float *d_grad, float *d_loss, hipStream_t stream);
+
+/* Forward pass only: d_y[p] = network(d_x[p]). */
+int merge_model_forward(const merge_model *m, const float *d_x, int64_t M, float *d_y,
+                        hipStream_t stream);
+
+/* Host copy of the parameters / replace them. */
+int merge_model_get_params(const merge_model *m, float *params_out);
+int merge_model_set_params(merge_model *m, const float *params);
+
+/* Learned-split co-rank of diagonals d_k[0..nk): same result as im_corank;
+ * d_probes (optional, may be NULL) receives the probes spent per diagonal. */
+int im_corank_learned(const void *data, int64_t L_A, int64_t L_B, int dtype,
+                      const merge_model *m, const int64_t *d_k, int64_t nk,
+                      int64_t *d_out, int32_t *d_probes, hipStream_t stream);
+
+/* In-place merge whose split searches use the model; bit-identical result. */
+int inplace_merge_learned(void *data, int64_t L_A, int64_t L_B, int dtype,
+                          const merge_model *m, hipStream_t stream);
+
+int merge_model_save(const merge_model *m, const char *path);
+int merge_model_load(merge_model **m, const char *path);
+int merge_model_free(merge_model *m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* INPLACE_MERGE_H */

@@ -1,0 +1,644 @@
+// im_capi.hip -- the extern "C" boundary (include/inplace_merge.h): argument
+// validation, workspace management, plan sizing and the launch sequence.
+// No host synchronisation on the merge path (only in checked mode, when
+// statistics are fetched, and when a model is trained).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/inplace_merge.h"
+#include "im_common.h"
+
+using namespace imerge;
+
+namespace {
+
+thread_local std::string g_err = "";
+thread_local im_stats g_stats = {};
+thread_local Counters *g_last_ctr = nullptr;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(IM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define IM_HIP(call, where)                          \
+    do {                                             \
+        hipError_t _e = (call);                      \
+        if (_e != hipSuccess) return hip_fail(_e, where); \
+    } while (0)
+
+int key_size(int dt) { return (dt == IM_INT32 || dt == IM_UINT32) ? 4 : 8; }
+bool valid_dtype(int dt) { return dt >= IM_INT32 && dt <= IM_UINT64; }
+
+bool checked_mode() {
+    const char *v = std::getenv("IM_CHECK");
+    return v && v[0] == '1';
+}
+
+struct DevState {
+    std::mutex mu;
+    void *ws = nullptr;          // library-owned workspace
+    size_t ws_bytes = 0;
+    void *user_ws = nullptr;     // caller-owned workspace (if set)
+    size_t user_bytes = 0;
+    hipEvent_t done = nullptr;   // last enqueued use of the workspace
+    bool done_valid = false;
+    int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // leaf grid by (key 4/8, payload 0/4/8)
+    int64_t *sort_off = nullptr; // offsets of the merge-sort passes
+    int64_t sort_off_cap = 0;
+};
+
+DevState g_dev[64];
+
+DevState *dev_state(int *dev_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (dev_out) *dev_out = dev;
+    return &g_dev[dev];
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Sizes and derived limits of one pipeline run.
+bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int64_t max_inst,
+               Plan *pl) {
+    int vi = ev == 0 ? 0 : (ev == 4 ? 1 : 2);
+    int ki = ek == 4 ? 0 : 1;
+    if (ds->grid[ki][vi] == 0) ds->grid[ki][vi] = leaf_grid(ek, ev);
+    int G = ds->grid[ki][vi];
+    if (G <= 0) return false;
+    int th, ipt;
+    size_t lds;
+    leaf_geometry(ek, ev, &th, &ipt, &lds);
+    const char *cap_env = std::getenv("IM_LEAF_TILES");   // test hook: tiles per leaf cap
+    int64_t tiles_per_leaf = G;
+    if (cap_env) {
+        long v = std::strtol(cap_env, nullptr, 10);
+        if (v >= 1 && v < tiles_per_leaf) tiles_per_leaf = v;
+    }
+    pl->n_inst = n_inst;
+    pl->total = total;
+    pl->tile = (int64_t)th * ipt;
+    pl->leaf_cap = tiles_per_leaf * pl->tile;
+    pl->grid_leaf = G;
+    if (max_inst <= 0 || max_inst > total) max_inst = total;
+    // Division levels: children are at most 9/16 of the parent (plus one for
+    // rounding), the last level only classifies.
+    int lv = 1;
+    double sz = (double)max_inst;
+    while (sz > (double)pl->leaf_cap && lv < kMaxLevels) {
+        sz = sz * 9.0 / 16.0 + 1.0;
+        ++lv;
+    }
+    pl->max_levels = lv;
+    int64_t per = total / pl->leaf_cap + 1;
+    pl->cap_nodes = std::max<int64_t>(n_inst, 2 * per) + 16;
+    pl->cap_rot = pl->cap_nodes;
+    pl->cap_leaves = n_inst + 2 * (int64_t)lv * per + 16;
+    pl->cap_tiles = total / pl->tile + pl->cap_leaves + 16;
+    return true;
+}
+
+size_t carve(const Plan &pl, void *base, Work *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? (char *)base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    Work x;
+    x.ctr = (Counters *)take(sizeof(Counters));
+    x.nodes[0] = (Node *)take(sizeof(Node) * pl.cap_nodes);
+    x.nodes[1] = (Node *)take(sizeof(Node) * pl.cap_nodes);
+    x.rot = (Rot *)take(sizeof(Rot) * pl.cap_rot);
+    x.leaves = (Leaf *)take(sizeof(Leaf) * pl.cap_leaves);
+    x.tile_start = (int64_t *)take(sizeof(int64_t) * pl.cap_leaves);
+    x.arrive = (unsigned *)take(sizeof(unsigned) * pl.cap_leaves);
+    x.tile_rank = (int64_t *)take(sizeof(int64_t) * pl.cap_tiles);
+    x.tile_leaf = (int32_t *)take(sizeof(int32_t) * pl.cap_tiles);
+    x.offsets1 = (int64_t *)take(sizeof(int64_t) * 4);
+    if (w) *w = x;
+    return off;
+}
+
+int acquire_ws(DevState *ds, size_t need, void **out) {
+    // IM_FAULT=alloc simulates a failed workspace allocation (tests of the
+    // error path); it applies whether or not the workspace must grow.
+    if (std::getenv("IM_FAULT") && std::strcmp(std::getenv("IM_FAULT"), "alloc") == 0)
+        return fail(IM_ERR_WORKSPACE, "workspace allocation failed (injected)");
+    if (ds->user_ws) {
+        if (ds->user_bytes < need)
+            return fail(IM_ERR_WORKSPACE, "workspace set by the caller is too small: need " +
+                                              std::to_string(need) + " bytes");
+        *out = ds->user_ws;
+        return IM_OK;
+    }
+    if (ds->ws_bytes < need) {
+        if (ds->ws) {
+            // earlier enqueued work may still use it
+            if (hipDeviceSynchronize() != hipSuccess) return fail(IM_ERR_HIP, "sync before realloc");
+            (void)hipFree(ds->ws);
+            ds->ws = nullptr;
+            ds->ws_bytes = 0;
+        }
+        size_t bytes = std::max(need, (size_t)1 << 20);
+        if (hipMalloc(&ds->ws, bytes) != hipSuccess) {
+            ds->ws = nullptr;
+            return fail(IM_ERR_WORKSPACE, "workspace allocation of " + std::to_string(bytes) +
+                                              " bytes failed");
+        }
+        ds->ws_bytes = bytes;
+    }
+    *out = ds->ws;
+    return IM_OK;
+}
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+// Order this call after the previous use of the shared workspace (other
+// streams) and record this use.
+int ws_enter(DevState *ds, hipStream_t s) {
+    if (ds->done == nullptr) {
+        if (hipEventCreateWithFlags(&ds->done, hipEventDisableTiming) != hipSuccess)
+            return fail(IM_ERR_HIP, "event create");
+    }
+    if (ds->done_valid && !stream_capturing(s)) IM_HIP(hipStreamWaitEvent(s, ds->done, 0), "stream wait");
+    return IM_OK;
+}
+
+int ws_leave(DevState *ds, hipStream_t s) {
+    if (!stream_capturing(s)) {
+        IM_HIP(hipEventRecord(ds->done, s), "event record");
+        ds->done_valid = true;
+    }
+    return IM_OK;
+}
+
+int read_error_bits(Counters *ctr, hipStream_t s, unsigned *bits) {
+    IM_HIP(hipStreamSynchronize(s), "synchronise (checked mode)");
+    unsigned v = 0;
+    IM_HIP(hipMemcpy(&v, &ctr->error, sizeof(v), hipMemcpyDeviceToHost), "read error flag");
+    *bits = v;
+    return IM_OK;
+}
+
+// The whole merge: division levels, leaf planning, tile co-ranks, leaf merge.
+int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
+                 int64_t n_inst, int64_t total, int64_t max_inst, int64_t la, int64_t lb,
+                 const MlpDev *mlp, hipStream_t s) {
+    int dev = 0;
+    DevState *ds = dev_state(&dev);
+    if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    std::lock_guard<std::mutex> lock(ds->mu);
+    const int ek = key_size(key_dt);
+    Plan pl;
+    if (!make_plan(ds, ek, ev, n_inst, total, max_inst, &pl))
+        return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
+    size_t need = carve(pl, nullptr, nullptr);
+    void *base = nullptr;
+    int rc = acquire_ws(ds, need, &base);
+    if (rc) return rc;
+    Work w;
+    carve(pl, base, &w);
+    rc = ws_enter(ds, s);
+    if (rc) return rc;
+
+    const bool check = checked_mode();
+    if (std::getenv("IM_FAULT") && std::strcmp(std::getenv("IM_FAULT"), "launch") == 0)
+        return fail(IM_ERR_HIP, "kernel launch failed (injected)");
+    IM_HIP(launch_init(pl, w, d_offsets, la, lb, s), "launch init");
+    const int64_t *offs = d_offsets ? d_offsets : w.offsets1;
+    if (check) {
+        IM_HIP(launch_check_sorted(key_dt, keys, offs, n_inst, w.ctr, s), "launch check");
+        unsigned bits = 0;
+        rc = read_error_bits(w.ctr, s, &bits);
+        if (rc) return rc;
+        if (bits & kErrOffsets) return fail(IM_ERR_INVALID_ARG, "offsets are not monotone");
+        if (bits & kErrNotSorted) return fail(IM_ERR_NOT_SORTED, "an input run is not ascending");
+    }
+    for (int lv = 0; lv < pl.max_levels; ++lv) {
+        IM_HIP(launch_split(key_dt, keys, offs, pl, w, lv, mlp, s), "launch split");
+        IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 0, s), "launch rotate A");
+        IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");
+    }
+    IM_HIP(launch_plan(pl, w, s), "launch plan");
+    IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
+    IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
+    rc = ws_leave(ds, s);
+    if (rc) return rc;
+
+    g_stats = im_stats{};
+    g_stats.leaf_capacity = pl.leaf_cap;
+    g_stats.tile = pl.tile;
+    g_stats.max_levels = pl.max_levels;
+    g_last_ctr = w.ctr;
+    if (check) {
+        unsigned bits = 0;
+        rc = read_error_bits(w.ctr, s, &bits);
+        if (rc) return rc;
+        if (bits) return fail(IM_ERR_DEVICE, "device-side check failed, error bits " +
+                                                 std::to_string(bits));
+    }
+    return IM_OK;
+}
+
+int check_common(const void *p, int64_t la, int64_t lb, int dt) {
+    if (!valid_dtype(dt)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (la < 0 || lb < 0) return fail(IM_ERR_INVALID_ARG, "negative run length");
+    if (la + lb > 0 && p == nullptr) return fail(IM_ERR_INVALID_ARG, "null data pointer");
+    if (la > (int64_t(1) << 46) || lb > (int64_t(1) << 46))
+        return fail(IM_ERR_INVALID_ARG, "run length too large");
+    return IM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Learned model object.
+// ---------------------------------------------------------------------------
+struct merge_model {
+    int device = 0;
+    MlpDev *d = nullptr;       // device copy used by the kernels
+    float *d_m = nullptr;      // Adam moments
+    float *d_v = nullptr;
+    float host[kMlpParams] = {};
+    float err_scale = 1.0f;
+};
+
+static uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static int model_upload(merge_model *m) {
+    MlpDev h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.p, m->host, sizeof(m->host));
+    h.err_scale = m->err_scale;
+    IM_HIP(hipMemcpy(m->d, &h, sizeof(h), hipMemcpyHostToDevice), "model upload");
+    return IM_OK;
+}
+
+extern "C" {
+
+const char *inplace_merge_last_error(void) { return g_err.c_str(); }
+
+int inplace_merge(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
+    return run_pipeline(dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
+                        nullptr, stream);
+}
+
+int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B, int key_dtype,
+                     int val_dtype, hipStream_t stream) {
+    int rc = check_common(keys, L_A, L_B, key_dtype);
+    if (rc) return rc;
+    if (!valid_dtype(val_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported payload dtype");
+    if (L_A + L_B > 0 && vals == nullptr) return fail(IM_ERR_INVALID_ARG, "null payload pointer");
+    if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
+    return run_pipeline(key_dtype, key_size(val_dtype), keys, vals, nullptr, 1, L_A + L_B,
+                        L_A + L_B, L_A, L_B, nullptr, stream);
+}
+
+int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n, int64_t total_elems,
+                          int64_t max_instance, int dtype, hipStream_t stream) {
+    if (!valid_dtype(dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (n < 0 || total_elems < 0 || max_instance < 0)
+        return fail(IM_ERR_INVALID_ARG, "negative count");
+    if (n == 0 || total_elems == 0) { g_err.clear(); return IM_OK; }
+    if (data == nullptr || d_offsets == nullptr) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (n >= (int64_t(1) << 31)) return fail(IM_ERR_INVALID_ARG, "too many instances");
+    return run_pipeline(dtype, 0, data, nullptr, d_offsets, n, total_elems, max_instance, 0, 0,
+                        nullptr, stream);
+}
+
+int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
+                             int64_t total_elems, int64_t max_instance, int key_dtype,
+                             int val_dtype, hipStream_t stream) {
+    if (!valid_dtype(key_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (!valid_dtype(val_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported payload dtype");
+    if (n < 0 || total_elems < 0 || max_instance < 0)
+        return fail(IM_ERR_INVALID_ARG, "negative count");
+    if (n == 0 || total_elems == 0) { g_err.clear(); return IM_OK; }
+    if (keys == nullptr || vals == nullptr || d_offsets == nullptr)
+        return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (n >= (int64_t(1) << 31)) return fail(IM_ERR_INVALID_ARG, "too many instances");
+    return run_pipeline(key_dtype, key_size(val_dtype), keys, vals, d_offsets, n, total_elems,
+                        max_instance, 0, 0, nullptr, stream);
+}
+
+int inplace_merge_sort(void *data, int64_t n, int dtype, hipStream_t stream) {
+    if (!valid_dtype(dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (n < 0) return fail(IM_ERR_INVALID_ARG, "negative length");
+    if (n <= 1) { g_err.clear(); return IM_OK; }
+    if (data == nullptr) return fail(IM_ERR_INVALID_ARG, "null data pointer");
+    DevState *ds = dev_state(nullptr);
+    if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    const int64_t tile = sort_tile_elems(key_size(dtype));
+    const int64_t max_inst_cnt = (n + 2 * tile - 1) / (2 * tile);
+    {
+        std::lock_guard<std::mutex> lock(ds->mu);
+        if (ds->sort_off_cap < 2 * max_inst_cnt + 1) {
+            if (ds->sort_off) {
+                if (hipDeviceSynchronize() != hipSuccess) return fail(IM_ERR_HIP, "sync");
+                (void)hipFree(ds->sort_off);
+                ds->sort_off = nullptr;
+            }
+            if (hipMalloc(&ds->sort_off, sizeof(int64_t) * (2 * max_inst_cnt + 1)) != hipSuccess) {
+                ds->sort_off = nullptr;
+                ds->sort_off_cap = 0;
+                return fail(IM_ERR_WORKSPACE, "sort offsets allocation failed");
+            }
+            ds->sort_off_cap = 2 * max_inst_cnt + 1;
+        }
+    }
+    IM_HIP(launch_tilesort(dtype, data, n, stream), "launch tile sort");
+    for (int64_t w = tile; w < n; w *= 2) {
+        int64_t ni = (n + 2 * w - 1) / (2 * w);
+        IM_HIP(launch_pass_offsets(n, w, ds->sort_off, ni, stream), "launch pass offsets");
+        int rc = run_pipeline(dtype, 0, data, nullptr, ds->sort_off, ni, n, std::min(n, 2 * w), 0, 0,
+                              nullptr, stream);
+        if (rc) return rc;
+    }
+    return IM_OK;
+}
+
+size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dtype) {
+    if (!valid_dtype(dtype) || total_elems < 0 || n_inst < 0) return 0;
+    DevState *ds = dev_state(nullptr);
+    if (!ds) return 0;
+    std::lock_guard<std::mutex> lock(ds->mu);
+    Plan pl;
+    if (!make_plan(ds, key_size(dtype), 8, std::max<int64_t>(n_inst, 1), std::max<int64_t>(total_elems, 1),
+                   0, &pl))
+        return 0;
+    size_t a = carve(pl, nullptr, nullptr);
+    Plan pl2;
+    if (!make_plan(ds, key_size(dtype), 0, std::max<int64_t>(n_inst, 1),
+                   std::max<int64_t>(total_elems, 1), 0, &pl2))
+        return 0;
+    return std::max(a, carve(pl2, nullptr, nullptr));
+}
+
+int inplace_merge_set_workspace(void *d_ws, size_t bytes) {
+    DevState *ds = dev_state(nullptr);
+    if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    std::lock_guard<std::mutex> lock(ds->mu);
+    if (d_ws != nullptr && bytes < 4096) return fail(IM_ERR_WORKSPACE, "workspace too small");
+    ds->user_ws = d_ws;
+    ds->user_bytes = d_ws ? bytes : 0;
+    g_err.clear();
+    return IM_OK;
+}
+
+int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream) {
+    if (!out) return fail(IM_ERR_INVALID_ARG, "null output");
+    *out = g_stats;
+    if (!g_last_ctr) return IM_OK;
+    IM_HIP(hipStreamSynchronize(stream), "synchronise for statistics");
+    Counters c;
+    IM_HIP(hipMemcpy(&c, g_last_ctr, sizeof(c), hipMemcpyDeviceToHost), "read counters");
+    out->levels_used = (int32_t)c.levels_used;
+    out->leaves = (int64_t)c.leaves;
+    out->tiles = (int64_t)c.tiles;
+    int64_t nrot = 0;
+    for (int l = 0; l < kMaxLevels; ++l) nrot += (int64_t)(c.level_rot[l] >> kRotCountShift);
+    out->rotations = nrot;
+    out->rotated_elems = (int64_t)c.rotated;
+    out->search_probes = (int64_t)c.probes;
+    out->searches = (int64_t)c.searches;
+    if (c.error) return fail(IM_ERR_DEVICE, "device error bits " + std::to_string(c.error));
+    return IM_OK;
+}
+
+int im_corank(const void *data, int64_t L_A, int64_t L_B, int dtype, const int64_t *d_k,
+              int64_t nk, int64_t *d_out, hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (nk < 0) return fail(IM_ERR_INVALID_ARG, "negative count");
+    if (nk == 0) return IM_OK;
+    if (!d_k || !d_out) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    IM_HIP(launch_corank(dtype, data, L_A, L_B, d_k, nk, d_out, nullptr, nullptr, stream),
+           "launch co-rank");
+    return IM_OK;
+}
+
+int im_rotate(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t stream) {
+    if (lx < 0 || ly < 0) return fail(IM_ERR_INVALID_ARG, "negative length");
+    if (elem_bytes != 4 && elem_bytes != 8) return fail(IM_ERR_UNSUPPORTED_DTYPE, "element size");
+    if (lx == 0 || ly == 0) return IM_OK;
+    if (!data) return fail(IM_ERR_INVALID_ARG, "null data pointer");
+    IM_HIP(launch_rotate_single(data, lx, ly, elem_bytes, stream), "launch rotate");
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned split.
+// ---------------------------------------------------------------------------
+int merge_model_create(merge_model **out, const float *params, uint64_t seed) {
+    if (!out) return fail(IM_ERR_INVALID_ARG, "null output");
+    merge_model *m = new (std::nothrow) merge_model();
+    if (!m) return fail(IM_ERR_WORKSPACE, "out of host memory");
+    if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(IM_ERR_HIP, "no device"); }
+    if (params) {
+        std::memcpy(m->host, params, sizeof(m->host));
+    } else {
+        // ReLU hinges spread over [0, 1): unit slopes, knots at h/H, small
+        // seeded output weights.
+        uint64_t st = seed;
+        for (int h = 0; h < kMlpHidden; ++h) {
+            double u = (double)(splitmix(st) >> 11) / 9007199254740992.0;
+            double v = (double)(splitmix(st) >> 11) / 9007199254740992.0;
+            m->host[h] = (float)(1.0 + 0.1 * (u - 0.5));
+            m->host[kMlpHidden + h] = (float)(-(double)h / kMlpHidden);
+            m->host[2 * kMlpHidden + h] = (float)(0.2 * (v - 0.5));
+        }
+        m->host[3 * kMlpHidden] = 0.0f;
+    }
+    if (hipMalloc(&m->d, sizeof(MlpDev)) != hipSuccess ||
+        hipMalloc(&m->d_m, sizeof(float) * kMlpParams) != hipSuccess ||
+        hipMalloc(&m->d_v, sizeof(float) * kMlpParams) != hipSuccess) {
+        merge_model_free(m);
+        return fail(IM_ERR_WORKSPACE, "model allocation failed");
+    }
+    int rc = model_upload(m);
+    if (rc) { merge_model_free(m); return rc; }
+    *out = m;
+    return IM_OK;
+}
+
+int merge_model_free(merge_model *m) {
+    if (!m) return IM_OK;
+    if (m->d) (void)hipFree(m->d);
+    if (m->d_m) (void)hipFree(m->d_m);
+    if (m->d_v) (void)hipFree(m->d_v);
+    delete m;
+    return IM_OK;
+}
+
+int merge_model_get_params(const merge_model *m, float *params_out) {
+    if (!m || !params_out) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    MlpDev h;
+    IM_HIP(hipMemcpy(&h, m->d, sizeof(h), hipMemcpyDeviceToHost), "model download");
+    std::memcpy(params_out, h.p, sizeof(h.p));
+    return IM_OK;
+}
+
+int merge_model_set_params(merge_model *m, const float *params) {
+    if (!m || !params) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    std::memcpy(m->host, params, sizeof(m->host));
+    return model_upload(m);
+}
+
+int merge_model_grad(const merge_model *m, const float *d_x, const float *d_t, int64_t M,
+                     float *d_grad, float *d_loss, hipStream_t stream) {
+    if (!m || !d_x || !d_t || !d_grad) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (M <= 0) return fail(IM_ERR_INVALID_ARG, "no samples");
+    int nb = mlp_grad_blocks(M);
+    float *partial = nullptr;
+    IM_HIP(hipMallocAsync((void **)&partial, sizeof(float) * (kMlpParams + 1) * nb, stream),
+           "alloc partials");
+    IM_HIP(launch_mlp_grad(m->d->p, d_x, d_t, M, partial, nb, stream), "launch grad");
+    IM_HIP(launch_mlp_reduce(partial, nb, d_grad, d_loss, stream), "launch reduce");
+    IM_HIP(hipFreeAsync(partial, stream), "free partials");
+    return IM_OK;
+}
+
+int merge_model_forward(const merge_model *m, const float *d_x, int64_t M, float *d_y,
+                        hipStream_t stream) {
+    if (!m || !d_x || !d_y) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (M <= 0) return IM_OK;
+    IM_HIP(launch_mlp_forward(m->d->p, d_x, M, d_y, stream), "launch forward");
+    return IM_OK;
+}
+
+int merge_model_train(merge_model *m, const void *data, int64_t L_A, int64_t L_B, int dtype,
+                      const merge_train_cfg *cfg, hipStream_t stream) {
+    if (!m || !cfg) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (L_A == 0 || L_B == 0) return fail(IM_ERR_INVALID_ARG, "both runs must be non-empty");
+    const int64_t M = cfg->samples;
+    if (M < 2 || cfg->steps < 0 || !(cfg->lr > 0.0f)) return fail(IM_ERR_INVALID_ARG, "bad config");
+    const int nb = mlp_grad_blocks(M);
+    int64_t *d_k = nullptr, *d_i = nullptr;
+    float *d_x = nullptr, *d_t = nullptr, *d_g = nullptr, *d_part = nullptr;
+    auto cleanup = [&]() {
+        if (d_k) (void)hipFree(d_k);
+        if (d_i) (void)hipFree(d_i);
+        if (d_x) (void)hipFree(d_x);
+        if (d_t) (void)hipFree(d_t);
+        if (d_g) (void)hipFree(d_g);
+        if (d_part) (void)hipFree(d_part);
+    };
+    if (hipMalloc(&d_k, sizeof(int64_t) * M) != hipSuccess ||
+        hipMalloc(&d_i, sizeof(int64_t) * M) != hipSuccess ||
+        hipMalloc(&d_x, sizeof(float) * M) != hipSuccess ||
+        hipMalloc(&d_t, sizeof(float) * M) != hipSuccess ||
+        hipMalloc(&d_g, sizeof(float) * kMlpParams) != hipSuccess ||
+        hipMalloc(&d_part, sizeof(float) * (kMlpParams + 1) * nb) != hipSuccess) {
+        cleanup();
+        return fail(IM_ERR_WORKSPACE, "training buffers");
+    }
+    hipError_t e = hipSuccess;
+    e = launch_mlp_samples(dtype, data, L_A, L_B, M, d_k, d_x, stream);
+    if (e == hipSuccess) e = launch_corank(dtype, data, L_A, L_B, d_k, M, d_i, nullptr, nullptr, stream);
+    if (e == hipSuccess) e = launch_mlp_targets(d_i, M, L_A, d_t, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->d_m, 0, sizeof(float) * kMlpParams, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->d_v, 0, sizeof(float) * kMlpParams, stream);
+    for (int st = 1; st <= cfg->steps && e == hipSuccess; ++st) {
+        e = launch_mlp_grad(m->d->p, d_x, d_t, M, d_part, nb, stream);
+        if (e == hipSuccess) e = launch_mlp_reduce(d_part, nb, d_g, nullptr, stream);
+        if (e == hipSuccess) e = launch_mlp_adam(m->d->p, d_g, m->d_m, m->d_v, cfg->lr, st, stream);
+    }
+    if (e == hipSuccess) e = launch_mlp_errscale(m->d->p, d_k, d_i, M, L_A, L_B, m->d, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    MlpDev h;
+    if (e == hipSuccess) e = hipMemcpy(&h, m->d, sizeof(h), hipMemcpyDeviceToHost);
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, "training");
+    std::memcpy(m->host, h.p, sizeof(m->host));
+    m->err_scale = h.err_scale;
+    return IM_OK;
+}
+
+int im_corank_learned(const void *data, int64_t L_A, int64_t L_B, int dtype, const merge_model *m,
+                      const int64_t *d_k, int64_t nk, int64_t *d_out, int32_t *d_probes,
+                      hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (!m) return fail(IM_ERR_INVALID_ARG, "null model");
+    if (nk < 0) return fail(IM_ERR_INVALID_ARG, "negative count");
+    if (nk == 0) return IM_OK;
+    if (!d_k || !d_out) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    IM_HIP(launch_corank(dtype, data, L_A, L_B, d_k, nk, d_out, m->d, d_probes, stream),
+           "launch learned co-rank");
+    return IM_OK;
+}
+
+int inplace_merge_learned(void *data, int64_t L_A, int64_t L_B, int dtype, const merge_model *m,
+                          hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (!m) return fail(IM_ERR_INVALID_ARG, "null model");
+    if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
+    return run_pipeline(dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B, m->d,
+                        stream);
+}
+
+int merge_model_save(const merge_model *m, const char *path) {
+    if (!m || !path) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    float p[kMlpParams];
+    int rc = merge_model_get_params(m, p);
+    if (rc) return rc;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(IM_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    const char magic[8] = {'I', 'M', 'M', 'L', 'P', '1', 0, 0};
+    int32_t hdr[2] = {kMlpHidden, kMlpParams};
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+              std::fwrite(p, sizeof(p), 1, f) == 1 &&
+              std::fwrite(&m->err_scale, sizeof(float), 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(IM_ERR_INVALID_ARG, "write failed");
+    return IM_OK;
+}
+
+int merge_model_load(merge_model **out, const char *path) {
+    if (!out || !path) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(IM_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t hdr[2];
+    float p[kMlpParams];
+    float es = 1.0f;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "IMMLP1", 6) == 0 &&
+              std::fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == kMlpHidden &&
+              hdr[1] == kMlpParams && std::fread(p, sizeof(p), 1, f) == 1 &&
+              std::fread(&es, sizeof(float), 1, f) == 1;
+    std::fclose(f);
+    if (!ok) return fail(IM_ERR_INVALID_ARG, "not a model file of this shape");
+    int rc = merge_model_create(out, p, 0);
+    if (rc) return rc;
+    (*out)->err_scale = es;
+    return model_upload(*out);
+}
+
+}  // extern "C"

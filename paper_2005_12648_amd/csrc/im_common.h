@@ -1,0 +1,160 @@
+// im_common.h -- internal declarations shared by the HIP translation units of
+// the in-place merge library.  Not installed; the public ABI is
+// include/inplace_merge.h.
+//
+// Pipeline (all on one stream, no host synchronisation):
+//   k_init      roots of the division tree, one per instance; counters reset.
+//   per level:  k_split   - per node: the early exits of Alg. 1 / Alg. 2-3,
+//                           then a split diagonal and its co-rank (Sec. 3.1),
+//                           children for the next level, one partition
+//                           exchange descriptor (Alg. 3 "shift"), or a leaf.
+//               k_rotate  - all exchanges of the level in one segmented
+//                           launch (phase A: block swap or the first two
+//                           reversals; phase B: the last reversal).
+//   k_plan      leaves -> workgroup tiles (prefix sum), barrier counters.
+//   k_tilerank  co-rank of every tile diagonal inside its leaf.
+//   k_leafmerge persistent kernel: each workgroup merges one tile in LDS; the
+//               tiles of one leaf meet at a per-leaf arrival counter between
+//               "all inputs read" and "outputs written" (Alg. 2/3 per-pair
+//               merge, several workgroups per pair).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace imerge {
+
+constexpr int kMaxLevels = 48;          // hard cap on enqueued division levels
+constexpr int kMlpHidden = 32;
+constexpr int kMlpParams = 3 * kMlpHidden + 1;
+constexpr int64_t kRotChunk = 4096;     // element pairs per exchange work item
+
+// A pair still to be divided: region [base, base+la+lb) of the buffer holds
+// the sorted A-part followed by the sorted B-part.  k0/i0 locate the node in
+// its instance's merge (global diagonal and co-rank of the node start).
+struct Node {
+    int64_t base, la, lb, k0, i0;
+    int32_t inst, pad;
+};
+
+// Partition exchange X|Y -> Y|X of [pos, pos+lx+ly).  lx == ly: one block
+// swap (a single linear-shifting step).  Otherwise three reversals.
+struct Rot {
+    int64_t pos, lx, ly;
+    int64_t w0;   // first work item of this exchange in its level
+    int64_t nw;   // work items
+};
+
+// A pair that is merged without further division.
+struct Leaf {
+    int64_t base, la, lb, k0, i0;
+    int32_t inst, ntiles;
+};
+
+// Device counters.  Zeroed by k_init at the start of every call.
+struct Counters {
+    unsigned long long level_nodes[kMaxLevels + 1];  // nodes at each level
+    unsigned long long level_rot[kMaxLevels];        // (count << 40) | work items
+    unsigned long long leaves;
+    unsigned long long tiles;
+    unsigned long long rotated;       // elements moved by exchanges
+    unsigned long long probes;        // key-pair probes of split searches
+    unsigned long long searches;      // split searches
+    unsigned long long levels_used;   // max level index that had nodes, +1
+    unsigned int error;               // nonzero: a device-side check failed
+    unsigned int pad;
+};
+
+constexpr int kRotCountShift = 40;
+constexpr unsigned long long kRotWorkMask = (1ull << kRotCountShift) - 1;
+
+// Error bits of Counters::error.
+constexpr unsigned kErrOversizeLeaf = 1u;   // a node still too large at the last level
+constexpr unsigned kErrBarrierSpin = 2u;    // per-leaf arrival wait gave up
+constexpr unsigned kErrCapacity = 4u;       // a descriptor array overflowed
+constexpr unsigned kErrNotSorted = 8u;      // checked mode: a run is unsorted
+constexpr unsigned kErrOffsets = 16u;       // checked mode: offsets not monotone
+
+// The learned split model as the kernels see it (device memory).
+struct MlpDev {
+    float p[kMlpParams];   // w1[H], b1[H], w2[H], b2
+    float err_scale;       // typical |prediction error| in A elements (>= 1)
+    float pad[2];
+};
+
+// Parameters common to one pipeline run.
+struct Plan {
+    int64_t n_inst;
+    int64_t total;          // bound of the elements in all instances
+    int64_t leaf_cap;       // largest pair merged without division (elements)
+    int64_t tile;           // elements per workgroup tile in the leaf merge
+    int32_t max_levels;     // division levels enqueued
+    int32_t grid_leaf;      // persistent grid of the leaf merge
+    int64_t cap_nodes, cap_rot, cap_leaves, cap_tiles;
+};
+
+// Workspace carve-up (device pointers).
+struct Work {
+    Counters *ctr;
+    Node *nodes[2];
+    Rot *rot;
+    Leaf *leaves;
+    int64_t *tile_start;     // per leaf: first tile index (exclusive scan)
+    int64_t *tile_rank;      // per tile: co-rank at the tile's first diagonal
+    int32_t *tile_leaf;      // per tile: its leaf
+    unsigned int *arrive;    // per leaf: arrival counter of the leaf barrier
+    int64_t *offsets1;       // [3] offsets of a single-instance call
+};
+
+// Key-type dispatch codes (match im_dtype of the public header).
+enum KeyCode { kI32 = 0, kU32 = 1, kI64 = 2, kU64 = 3 };
+
+// ---- launchers (defined in the .hip files) --------------------------------
+hipError_t launch_init(const Plan &pl, const Work &w, const int64_t *d_offsets,
+                       int64_t la, int64_t lb, hipStream_t s);
+hipError_t launch_split(int key, void *data, const int64_t *d_offsets, const Plan &pl,
+                        const Work &w, int level, const MlpDev *mlp, hipStream_t s);
+hipError_t launch_rotate(int esize_k, int esize_v, void *keys, void *vals, const Plan &pl,
+                         const Work &w, int level, int phase, hipStream_t s);
+hipError_t launch_plan(const Plan &pl, const Work &w, hipStream_t s);
+hipError_t launch_tilerank(int key, void *data, const int64_t *d_offsets, const Plan &pl,
+                           const Work &w, const MlpDev *mlp, hipStream_t s);
+hipError_t launch_leafmerge(int key, int esize_v, void *keys, void *vals, const Plan &pl,
+                            const Work &w, hipStream_t s);
+// Tile geometry of the leaf merge for a (key size, payload size) pair.
+void leaf_geometry(int esize_k, int esize_v, int *threads, int *ipt, size_t *lds_bytes);
+int leaf_grid(int esize_k, int esize_v);   // persistent grid (resident workgroups)
+const void *leaf_kernel_ptr(int key, int esize_v);
+
+hipError_t launch_corank(int key, const void *data, int64_t la, int64_t lb, const int64_t *d_k,
+                         int64_t nk, int64_t *d_out, const MlpDev *mlp, int32_t *d_probes,
+                         hipStream_t s);
+hipError_t launch_rotate_single(void *data, int64_t lx, int64_t ly, int esize, hipStream_t s);
+hipError_t launch_check_sorted(int key, const void *data, const int64_t *d_offsets,
+                               int64_t n_inst, Counters *ctr, hipStream_t s);
+
+// Merge sort helpers.
+int sort_tile_elems(int esize);
+hipError_t launch_tilesort(int key, void *data, int64_t n, hipStream_t s);
+hipError_t launch_pass_offsets(int64_t n, int64_t width, int64_t *d_off, int64_t n_inst,
+                               hipStream_t s);
+
+// MLP kernels.
+hipError_t launch_mlp_grad(const float *d_params, const float *d_x, const float *d_t, int64_t m,
+                           float *d_partial, int nblocks, hipStream_t s);
+hipError_t launch_mlp_reduce(const float *d_partial, int nblocks, float *d_grad, float *d_loss,
+                             hipStream_t s);
+hipError_t launch_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v,
+                           float lr, int step, hipStream_t s);
+hipError_t launch_mlp_forward(const float *d_params, const float *d_x, int64_t m, float *d_y,
+                              hipStream_t s);
+hipError_t launch_mlp_samples(int key, const void *data, int64_t la, int64_t lb, int64_t m,
+                              int64_t *d_k, float *d_x, hipStream_t s);
+hipError_t launch_mlp_targets(const int64_t *d_i, int64_t m, int64_t la, float *d_t,
+                              hipStream_t s);
+hipError_t launch_mlp_errscale(const float *d_params, const int64_t *d_k, const int64_t *d_i,
+                               int64_t m, int64_t la, int64_t lb, MlpDev *d_model,
+                               hipStream_t s);
+int mlp_grad_blocks(int64_t m);
+
+}  // namespace imerge

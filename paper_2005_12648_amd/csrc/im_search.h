@@ -1,0 +1,102 @@
+// im_search.h -- device-side split searches.
+//
+// Co-rank (the exact split of Sec. 3.1 -- the "optimal" pivot search --
+// generalised to an arbitrary output rank k): the number i of A elements
+// among the first k outputs of the stable merge of A and B.  With
+// P(m) := A[m] <= B[k-1-m], P is true then false on
+// [max(0, k-L_B), min(k, L_A)), and i is the first m where it is false (or
+// the upper bound).  Ties therefore take A first.
+//
+// The learned variant starts from a network prediction and brackets the
+// answer by an exponential search before the same binary search; it returns
+// exactly the same i.
+#pragma once
+#include "im_common.h"
+
+namespace imerge {
+
+template <typename K>
+__device__ __forceinline__ int64_t corank_binary(const K *__restrict__ A, int64_t la,
+                                                 const K *__restrict__ B, int64_t lb,
+                                                 int64_t k, int64_t lo, int64_t hi,
+                                                 uint32_t &probes) {
+    // Invariant: every m < lo has P(m) true, every m >= hi has P(m) false.
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        ++probes;
+        if (A[mid] <= B[k - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename K>
+__device__ __forceinline__ int64_t corank_plain(const K *__restrict__ A, int64_t la,
+                                                const K *__restrict__ B, int64_t lb, int64_t k,
+                                                uint32_t &probes) {
+    int64_t lo = k > lb ? k - lb : 0;
+    int64_t hi = k < la ? k : la;
+    return corank_binary(A, la, B, lb, k, lo, hi, probes);
+}
+
+// fp32 forward pass of the 1 -> H -> 1 ReLU network.
+__device__ __forceinline__ float mlp_eval(const MlpDev *__restrict__ M, float x) {
+    float y = M->p[3 * kMlpHidden];
+#pragma unroll
+    for (int h = 0; h < kMlpHidden; ++h) {
+        float z = fmaf(M->p[h], x, M->p[kMlpHidden + h]);
+        y = fmaf(M->p[2 * kMlpHidden + h], fmaxf(z, 0.0f), y);
+    }
+    return y;
+}
+
+// Learned co-rank.  kg: global diagonal of the instance (size n_inst, A size
+// la_inst); i0: global co-rank of the start of the searched sub-problem
+// (A/B here are that sub-problem's parts), k: local diagonal.
+template <typename K>
+__device__ __forceinline__ int64_t corank_learned(const K *__restrict__ A, int64_t la,
+                                                  const K *__restrict__ B, int64_t lb, int64_t k,
+                                                  const MlpDev *__restrict__ M, int64_t kg,
+                                                  int64_t n_inst, int64_t la_inst, int64_t i0,
+                                                  uint32_t &probes) {
+    int64_t lo = k > lb ? k - lb : 0;
+    int64_t hi = k < la ? k : la;
+    if (hi - lo <= 1) return corank_binary(A, la, B, lb, k, lo, hi, probes);
+    float x = n_inst > 0 ? (float)((double)kg / (double)n_inst) : 0.0f;
+    float y = mlp_eval(M, x);
+    double gd = (double)y * (double)la_inst - (double)i0;
+    int64_t g;
+    if (!(gd == gd)) g = lo;                     // NaN prediction: start at lo
+    else if (gd <= (double)lo) g = lo;
+    else if (gd >= (double)hi) g = hi;
+    else g = (int64_t)llrint(gd);
+    int64_t step = (int64_t)M->err_scale;
+    if (step < 1) step = 1;
+    int64_t blo, bhi;
+    if (g < hi && (++probes, A[g] <= B[k - 1 - g])) {
+        // answer > g: gallop to the right
+        blo = g + 1;
+        for (;;) {
+            int64_t m = g + step;
+            if (m >= hi) { bhi = hi; break; }
+            ++probes;
+            if (!(A[m] <= B[k - 1 - m])) { bhi = m; break; }
+            blo = m + 1;
+            step <<= 1;
+        }
+    } else {
+        // answer <= g: gallop to the left
+        bhi = g;
+        for (;;) {
+            int64_t m = g - step;
+            if (m < lo) { blo = lo; break; }
+            ++probes;
+            if (A[m] <= B[k - 1 - m]) { blo = m + 1; break; }
+            bhi = m;
+            step <<= 1;
+        }
+    }
+    return corank_binary(A, la, B, lb, k, blo, bhi, probes);
+}
+
+}  // namespace imerge

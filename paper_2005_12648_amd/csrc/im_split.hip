@@ -1,0 +1,368 @@
+// im_split.hip -- division stage: tree roots, per-level split of every node,
+// tile co-ranks of the leaves, and the stand-alone co-rank entry point.
+//
+// Sec. 3 divides A B into pairs A_0 B_0 ... A_{T-1} B_{T-1} whose elements
+// are ordered pair to pair.  Alg. 3 (sRecPar) does it recursively: find the
+// split of the current pair, exchange the two middle partitions (A_1 | B_0),
+// recurse on both halves.  Here every level of that recursion is one launch
+// over all nodes of the level (all instances of a batch included), and the
+// exchanges of a level are one segmented launch (im_rotate.hip).
+//
+// Split rule of a node with parts la, lb (S = la + lb):
+//   * early exits first, exactly the tests of Alg. 1 (lines that return
+//     before the search) and of the entry of Alg. 2/3: an empty part, or
+//     A[last] <= B[0], leaves the node as it is; A[0] > B[last] needs a single
+//     exchange B|A and no merge;
+//   * S <= leaf capacity: the node is a leaf (merged in LDS, im_leaf.hip);
+//   * otherwise the split diagonal is k = la when max(la, lb) <= 9/16 S --
+//     then the two exchanged partitions have the same length (la - i == j),
+//     so the exchange is a single block swap -- else k = S/2 (balanced
+//     halves, the balance goal of Sec. 3.1) and the exchange takes three
+//     reversals.  Children are at most 9/16 of the parent either way.
+#include "im_common.h"
+#include "im_search.h"
+
+namespace imerge {
+
+constexpr int kSplitThreads = 256;
+
+__global__ void k_init(Counters *ctr, Node *nodes0, const int64_t *__restrict__ offsets,
+                       int64_t n_inst, int64_t la, int64_t lb, int64_t *off1) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    constexpr int kWords = (int)(sizeof(Counters) / sizeof(unsigned long long));
+    if (gid < kWords) {
+        // level_nodes[0] is the first word: it starts at the number of roots.
+        reinterpret_cast<unsigned long long *>(ctr)[gid] =
+            gid == 0 ? (unsigned long long)n_inst : 0ull;
+    }
+    if (offsets == nullptr) {
+        // single instance: A = [0, la), B = [la, la+lb)
+        if (gid == 0) {
+            off1[0] = 0;
+            off1[1] = la;
+            off1[2] = la + lb;
+            Node nd;
+            nd.base = 0; nd.la = la; nd.lb = lb; nd.k0 = 0; nd.i0 = 0; nd.inst = 0; nd.pad = 0;
+            nodes0[0] = nd;
+        }
+        return;
+    }
+    for (int64_t q = gid; q < n_inst; q += stride) {
+        int64_t o0 = offsets[2 * q], o1 = offsets[2 * q + 1], o2 = offsets[2 * q + 2];
+        Node nd;
+        nd.base = o0;
+        nd.la = o1 - o0;
+        nd.lb = o2 - o1;
+        if (nd.la < 0 || nd.lb < 0) { nd.la = 0; nd.lb = 0; }   // never index a bad instance
+        nd.k0 = 0; nd.i0 = 0; nd.inst = (int32_t)q; nd.pad = 0;
+        nodes0[q] = nd;
+    }
+}
+
+__device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int level, int64_t pos,
+                                         int64_t lx, int64_t ly) {
+    int64_t nw;
+    if (lx == ly) {
+        nw = (lx + kRotChunk - 1) / kRotChunk;
+    } else {
+        int64_t a = (lx / 2 + kRotChunk - 1) / kRotChunk + (ly / 2 + kRotChunk - 1) / kRotChunk;
+        int64_t b = ((lx + ly) / 2 + kRotChunk - 1) / kRotChunk;
+        nw = a > b ? a : b;
+    }
+    unsigned long long packed = atomicAdd(&w.ctr->level_rot[level],
+                                          (1ull << kRotCountShift) | (unsigned long long)nw);
+    unsigned long long slot = packed >> kRotCountShift;
+    if ((int64_t)slot >= pl.cap_rot) {
+        atomicOr(&w.ctr->error, kErrCapacity);
+        return;
+    }
+    Rot r;
+    r.pos = pos; r.lx = lx; r.ly = ly;
+    r.w0 = (int64_t)(packed & kRotWorkMask);
+    r.nw = nw;
+    w.rot[slot] = r;
+    atomicAdd(&w.ctr->rotated, (unsigned long long)(lx + ly));
+}
+
+__device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const Node &nd) {
+    unsigned long long slot = atomicAdd(&w.ctr->leaves, 1ull);
+    if ((int64_t)slot >= pl.cap_leaves) {
+        atomicOr(&w.ctr->error, kErrCapacity);
+        return;
+    }
+    Leaf lf;
+    lf.base = nd.base; lf.la = nd.la; lf.lb = nd.lb; lf.k0 = nd.k0; lf.i0 = nd.i0;
+    lf.inst = nd.inst; lf.ntiles = 0;
+    w.leaves[slot] = lf;
+}
+
+template <typename K, bool LEARNED>
+__global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ data,
+                                                         const int64_t *__restrict__ offsets,
+                                                         Plan pl, Work w, int level,
+                                                         const MlpDev *__restrict__ mlp) {
+    const unsigned long long cnt = w.ctr->level_nodes[level];
+    const Node *in = w.nodes[level & 1];
+    Node *out = w.nodes[(level + 1) & 1];
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (gid == 0 && cnt > 0) atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
+    uint32_t probes = 0, searches = 0;
+    for (int64_t idx = gid; idx < (int64_t)cnt && idx < pl.cap_nodes; idx += stride) {
+        Node nd = in[idx];
+        const int64_t la = nd.la, lb = nd.lb;
+        if (la == 0 || lb == 0) continue;                       // nothing to merge
+        const K *A = data + nd.base;
+        const K *B = A + la;
+        if (A[la - 1] <= B[0]) continue;                        // already in order
+        if (A[0] > B[lb - 1]) {                                 // every B before every A
+            emit_rot(pl, w, level, nd.base, la, lb);
+            continue;
+        }
+        const int64_t S = la + lb;
+        if (S <= pl.leaf_cap) {
+            emit_leaf(pl, w, nd);
+            continue;
+        }
+        if (level + 1 >= pl.max_levels) {                       // depth bound violated
+            atomicOr(&w.ctr->error, kErrOversizeLeaf);
+            continue;
+        }
+        const int64_t mx = la > lb ? la : lb;
+        const int64_t k = (mx * 16 <= S * 9) ? la : S / 2;
+        int64_t i;
+        ++searches;
+        if (LEARNED) {
+            int64_t o0 = offsets[2 * nd.inst], o1 = offsets[2 * nd.inst + 1],
+                    o2 = offsets[2 * nd.inst + 2];
+            i = corank_learned(A, la, B, lb, k, mlp, nd.k0 + k, o2 - o0, o1 - o0, nd.i0, probes);
+        } else {
+            i = corank_plain(A, la, B, lb, k, probes);
+        }
+        const int64_t j = k - i;
+        // Alg. 3 "shift": exchange A[i, la) and B[0, j) -> ... A_0 B_0 A_1 B_1
+        if (la - i > 0 && j > 0) emit_rot(pl, w, level, nd.base + i, la - i, j);
+        unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level + 1], 2ull);
+        if ((int64_t)slot + 1 >= pl.cap_nodes) {
+            atomicOr(&w.ctr->error, kErrCapacity);
+            continue;
+        }
+        Node l, r;
+        l.base = nd.base; l.la = i; l.lb = j; l.k0 = nd.k0; l.i0 = nd.i0; l.inst = nd.inst; l.pad = 0;
+        r.base = nd.base + k; r.la = la - i; r.lb = lb - j; r.k0 = nd.k0 + k; r.i0 = nd.i0 + i;
+        r.inst = nd.inst; r.pad = 0;
+        out[slot] = l;
+        out[slot + 1] = r;
+    }
+    if (searches) {
+        atomicAdd(&w.ctr->searches, (unsigned long long)searches);
+        atomicAdd(&w.ctr->probes, (unsigned long long)probes);
+    }
+}
+
+// Tile co-ranks: tile t of leaf l starts at local diagonal (t - tile_start[l]) * tile.
+template <typename K, bool LEARNED>
+__global__ __launch_bounds__(kSplitThreads) void k_tilerank(const K *__restrict__ data,
+                                                            const int64_t *__restrict__ offsets,
+                                                            Plan pl, Work w,
+                                                            const MlpDev *__restrict__ mlp) {
+    const int64_t ntiles = (int64_t)w.ctr->tiles;
+    int64_t nleaves = (int64_t)w.ctr->leaves;
+    if (nleaves > pl.cap_leaves) nleaves = pl.cap_leaves;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t probes = 0, searches = 0;
+    for (int64_t t = gid; t < ntiles && t < pl.cap_tiles; t += stride) {
+        // leaf = last l with tile_start[l] <= t
+        int64_t lo = 0, hi = nleaves;
+        while (hi - lo > 1) {
+            int64_t mid = (lo + hi) >> 1;
+            if (w.tile_start[mid] <= t) lo = mid; else hi = mid;
+        }
+        const Leaf lf = w.leaves[lo];
+        const int64_t d = (t - w.tile_start[lo]) * pl.tile;
+        int64_t i = 0;
+        if (d > 0) {
+            const K *A = data + lf.base;
+            const K *B = A + lf.la;
+            ++searches;
+            if (LEARNED) {
+                int64_t o0 = offsets[2 * lf.inst], o1 = offsets[2 * lf.inst + 1],
+                        o2 = offsets[2 * lf.inst + 2];
+                i = corank_learned(A, lf.la, B, lf.lb, d, mlp, lf.k0 + d, o2 - o0, o1 - o0,
+                                   lf.i0, probes);
+            } else {
+                i = corank_plain(A, lf.la, B, lf.lb, d, probes);
+            }
+        }
+        w.tile_rank[t] = i;
+        w.tile_leaf[t] = (int32_t)lo;
+    }
+    if (searches) {
+        atomicAdd(&w.ctr->searches, (unsigned long long)searches);
+        atomicAdd(&w.ctr->probes, (unsigned long long)probes);
+    }
+}
+
+// Stand-alone co-rank of a list of diagonals (one lane per diagonal).
+template <typename K, bool LEARNED>
+__global__ __launch_bounds__(kSplitThreads) void k_corank(const K *__restrict__ data, int64_t la,
+                                                          int64_t lb, const int64_t *__restrict__ ks,
+                                                          int64_t nk, int64_t *__restrict__ out,
+                                                          const MlpDev *__restrict__ mlp,
+                                                          int32_t *__restrict__ probes_out) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const K *A = data;
+    const K *B = data + la;
+    for (int64_t p = gid; p < nk; p += stride) {
+        int64_t k = ks[p];
+        uint32_t probes = 0;
+        int64_t i;
+        if (k < 0 || k > la + lb) {
+            i = -1;                                  // out-of-range diagonal
+        } else if (LEARNED) {
+            i = corank_learned(A, la, B, lb, k, mlp, k, la + lb, la, 0, probes);
+        } else {
+            i = corank_plain(A, la, B, lb, k, probes);
+        }
+        out[p] = i;
+        if (probes_out) probes_out[p] = (int32_t)probes;
+    }
+}
+
+// Checked mode: every run ascending, every instance's offsets monotone.
+template <typename K>
+__global__ void k_check_sorted(const K *__restrict__ data, const int64_t *__restrict__ offsets,
+                               int64_t n_inst, Counters *ctr) {
+    for (int64_t q = blockIdx.x; q < n_inst; q += gridDim.x) {
+        int64_t o0 = offsets[2 * q], o1 = offsets[2 * q + 1], o2 = offsets[2 * q + 2];
+        if (o1 < o0 || o2 < o1) {
+            if (threadIdx.x == 0) atomicOr(&ctr->error, kErrOffsets);
+            continue;
+        }
+        bool bad = false;
+        for (int64_t x = o0 + threadIdx.x; x + 1 < o2; x += blockDim.x) {
+            if (x + 1 == o1) continue;                       // the A|B seam is not a run
+            if (data[x + 1] < data[x]) bad = true;
+        }
+        if (bad) atomicOr(&ctr->error, kErrNotSorted);
+    }
+}
+
+static int grid_for(int64_t items, int threads, int cap) {
+    int64_t g = (items + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_init(const Plan &pl, const Work &w, const int64_t *d_offsets, int64_t la,
+                       int64_t lb, hipStream_t s) {
+    int64_t items = pl.n_inst > 256 ? pl.n_inst : 256;
+    int g = grid_for(items, 256, 4096);
+    hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, s, w.ctr, w.nodes[0], d_offsets, pl.n_inst,
+                       la, lb, w.offsets1);
+    return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t split_t(const void *data, const int64_t *offs, const Plan &pl, const Work &w,
+                          int level, const MlpDev *mlp, hipStream_t s) {
+    int g = grid_for(pl.cap_nodes, kSplitThreads, 2048);
+    if (mlp)
+        hipLaunchKernelGGL((k_split<K, true>), dim3(g), dim3(kSplitThreads), 0, s,
+                           (const K *)data, offs, pl, w, level, mlp);
+    else
+        hipLaunchKernelGGL((k_split<K, false>), dim3(g), dim3(kSplitThreads), 0, s,
+                           (const K *)data, offs, pl, w, level, mlp);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(int key, void *data, const int64_t *offs, const Plan &pl, const Work &w,
+                        int level, const MlpDev *mlp, hipStream_t s) {
+    switch (key) {
+        case kI32: return split_t<int32_t>(data, offs, pl, w, level, mlp, s);
+        case kU32: return split_t<uint32_t>(data, offs, pl, w, level, mlp, s);
+        case kI64: return split_t<int64_t>(data, offs, pl, w, level, mlp, s);
+        case kU64: return split_t<uint64_t>(data, offs, pl, w, level, mlp, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename K>
+static hipError_t tilerank_t(const void *data, const int64_t *offs, const Plan &pl, const Work &w,
+                             const MlpDev *mlp, hipStream_t s) {
+    int g = grid_for(pl.cap_tiles, kSplitThreads, 4096);
+    if (mlp)
+        hipLaunchKernelGGL((k_tilerank<K, true>), dim3(g), dim3(kSplitThreads), 0, s,
+                           (const K *)data, offs, pl, w, mlp);
+    else
+        hipLaunchKernelGGL((k_tilerank<K, false>), dim3(g), dim3(kSplitThreads), 0, s,
+                           (const K *)data, offs, pl, w, mlp);
+    return hipGetLastError();
+}
+
+hipError_t launch_tilerank(int key, void *data, const int64_t *offs, const Plan &pl,
+                           const Work &w, const MlpDev *mlp, hipStream_t s) {
+    switch (key) {
+        case kI32: return tilerank_t<int32_t>(data, offs, pl, w, mlp, s);
+        case kU32: return tilerank_t<uint32_t>(data, offs, pl, w, mlp, s);
+        case kI64: return tilerank_t<int64_t>(data, offs, pl, w, mlp, s);
+        case kU64: return tilerank_t<uint64_t>(data, offs, pl, w, mlp, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename K>
+static hipError_t corank_t(const void *data, int64_t la, int64_t lb, const int64_t *ks, int64_t nk,
+                           int64_t *out, const MlpDev *mlp, int32_t *probes, hipStream_t s) {
+    int g = grid_for(nk, kSplitThreads, 8192);
+    if (mlp)
+        hipLaunchKernelGGL((k_corank<K, true>), dim3(g), dim3(kSplitThreads), 0, s,
+                           (const K *)data, la, lb, ks, nk, out, mlp, probes);
+    else
+        hipLaunchKernelGGL((k_corank<K, false>), dim3(g), dim3(kSplitThreads), 0, s,
+                           (const K *)data, la, lb, ks, nk, out, mlp, probes);
+    return hipGetLastError();
+}
+
+hipError_t launch_corank(int key, const void *data, int64_t la, int64_t lb, const int64_t *d_k,
+                         int64_t nk, int64_t *d_out, const MlpDev *mlp, int32_t *d_probes,
+                         hipStream_t s) {
+    switch (key) {
+        case kI32: return corank_t<int32_t>(data, la, lb, d_k, nk, d_out, mlp, d_probes, s);
+        case kU32: return corank_t<uint32_t>(data, la, lb, d_k, nk, d_out, mlp, d_probes, s);
+        case kI64: return corank_t<int64_t>(data, la, lb, d_k, nk, d_out, mlp, d_probes, s);
+        case kU64: return corank_t<uint64_t>(data, la, lb, d_k, nk, d_out, mlp, d_probes, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_check_sorted(int key, const void *data, const int64_t *d_offsets,
+                               int64_t n_inst, Counters *ctr, hipStream_t s) {
+    int g = (int)(n_inst < 4096 ? (n_inst < 1 ? 1 : n_inst) : 4096);
+    switch (key) {
+        case kI32:
+            hipLaunchKernelGGL(k_check_sorted<int32_t>, dim3(g), dim3(256), 0, s,
+                               (const int32_t *)data, d_offsets, n_inst, ctr);
+            break;
+        case kU32:
+            hipLaunchKernelGGL(k_check_sorted<uint32_t>, dim3(g), dim3(256), 0, s,
+                               (const uint32_t *)data, d_offsets, n_inst, ctr);
+            break;
+        case kI64:
+            hipLaunchKernelGGL(k_check_sorted<int64_t>, dim3(g), dim3(256), 0, s,
+                               (const int64_t *)data, d_offsets, n_inst, ctr);
+            break;
+        case kU64:
+            hipLaunchKernelGGL(k_check_sorted<uint64_t>, dim3(g), dim3(256), 0, s,
+                               (const uint64_t *)data, d_offsets, n_inst, ctr);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace imerge
