@@ -1,0 +1,372 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X in-place merge (one GPU).
+
+A step is one whole in-place merge -- division levels, tile co-ranks and the
+leaf merge -- of int32 runs L_A = L_B = 2^27 (uniform in [0, 2^31), each run
+sorted), the input already resident in HBM.  The merge works in place, so the
+K timed steps run on K separate copies of the input prepared before the timed
+region; nothing is restored inside it.
+
+Printed on stdout: ONE JSON line with the headline (Gelem/s), the roofline of
+the dominant kernel (per-stage HIP events recorded on the merge's stream over
+the timed region), the CPU oracle timed on this host's cores, and the other
+forms side by side (batched merge of 4096 instances vs 4096 plain calls,
+in-place merge sort of 2^28 int32, learned split vs plain on int64 2^28+2^28,
+key+payload, skewed and duplicate-heavy variants).  Every GPU result is
+compared with the CPU oracle; mismatch counts are part of the line.
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+SEED = 12648
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def src_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "leafmerge": ["paper_2005_12648_amd/csrc/im_leaf.hip", "paper_2005_12648_amd/csrc/im_common.h"],
+    "rotate": ["paper_2005_12648_amd/csrc/im_rotate.hip", "paper_2005_12648_amd/csrc/im_common.h"],
+    "split": ["paper_2005_12648_amd/csrc/im_split.hip", "paper_2005_12648_amd/csrc/im_search.h"],
+    "tilerank": ["paper_2005_12648_amd/csrc/im_split.hip", "paper_2005_12648_amd/csrc/im_search.h"],
+    "plan": ["paper_2005_12648_amd/csrc/im_leaf.hip"],
+}
+
+
+def traffic_from_profile(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != src_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self.torch.cuda.synchronize()
+        self.ms = self.a.elapsed_time(self.b)
+
+
+def cpu_oracle_time(fn, budget_s: float):
+    """Run the oracle until budget_s of wall time is spent (at least once)."""
+    times, out = [], None
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        out = fn()
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start >= budget_s:
+            break
+    return out, float(np.median(times)), len(times)
+
+
+def mismatches(got_t, want_np):
+    got = got_t.cpu().numpy()
+    return int(np.count_nonzero(got != want_np))
+
+
+def timed_merges(torch, im, pristine, la, steps, warmup, fn=None, profile=False):
+    """K merges on K prepared copies; returns (ms per step, stage profile, buffers)."""
+    fn = fn or (lambda b: im.inplace_merge(b, la))
+    bufs = [torch.empty_like(pristine) for _ in range(steps)]
+    for _ in range(warmup):
+        bufs[0].copy_(pristine)
+        fn(bufs[0])
+    for b in bufs:
+        b.copy_(pristine)
+    torch.cuda.synchronize()
+    if profile:
+        im.profile_read()          # drop anything recorded before
+        im.profile(True)
+    with Timer(torch) as t:
+        for k in range(steps):
+            fn(bufs[k])
+    prof = None
+    if profile:
+        prof = im.profile_read()
+        im.profile(False)
+    return t.ms / steps, prof, bufs
+
+
+def roofline(prof, stats, esize, steps, workload):
+    """Dominant kernel by total time; algorithmic bytes per launch / avg launch time."""
+    per_call = {
+        # every leaf element is read once and written once
+        "leafmerge": 2.0 * stats["leaf_elems"] * esize,
+        # block swap: read + write each exchanged element once; three
+        # reversals: twice
+        "rotate": 2.0 * esize * (stats["rotated_elems"] + stats["reversed_elems"]),
+        # two key loads per probe
+        "split": 2.0 * esize * stats["search_probes"],
+        "tilerank": 0.0,
+        "plan": 0.0,
+    }
+    stage_ms = {k: v[0] for k, v in prof.items()}
+    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    ms, launches = prof[dom]
+    launches = max(int(launches), 1)
+    avg_launch_ms = ms / launches
+    bytes_per_launch = per_call[dom] * steps / launches
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(dom, workload)
+    return {
+        "kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic, "avg_launch_ms": round(avg_launch_ms, 5),
+        "launches_per_step": launches / steps,
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+        "stage_ms_per_step": {k: round(v / steps, 5) for k, v in stage_ms.items()},
+    }
+
+
+def bench_headline(torch, im, oracle, gen, dev, args):
+    la = lb = 2 ** 27
+    n = la + lb
+    log("c2: generating int32 2^27 + 2^27 on the device")
+    pristine = gen.torch_pair_uniform(la, lb, SEED + 20, dev)
+    ms, prof, bufs = timed_merges(torch, im, pristine, la, args.steps, args.warmup, profile=True)
+    stats = im.fetch_stats()
+    log("c2: %.3f ms/step, %.1f Gelem/s" % (ms, n / ms / 1e6))
+    res = {"ms": ms, "prof": prof, "stats": stats, "n": n}
+    cpu = None
+    if not args.no_cpu:
+        host = pristine.cpu().numpy()
+        log("c2: CPU oracle (single thread) for %.0f s" % args.cpu_seconds)
+        want, med_s, reps = cpu_oracle_time(lambda: oracle.merge(host, la), args.cpu_seconds)
+        cpu = {"value": round(n / med_s / 1e9, 4), "unit": "Gelem/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "full workload (int32 2^27+2^27), %d repetitions, median; "
+                         "stable two-finger merge into a fresh buffer + copy back" % reps,
+               "host_cores_available": os.cpu_count()}
+        res["mismatch"] = mismatches(bufs[0], want) + mismatches(bufs[-1], want)
+        log("c2: mismatches vs oracle:", res["mismatch"])
+    res["cpu"] = cpu
+    del bufs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_variant(torch, im, oracle, gen, dev, name, steps):
+    """Skewed / duplicate-heavy int32 and the key+payload form."""
+    if name == "c3_kv":
+        la = lb = 2 ** 26
+        keys = gen.torch_pair_uniform(la, lb, SEED + 30, dev, hi=4096, dtype=torch.int64)
+        vals = torch.arange(la + lb, dtype=torch.int32, device=dev).to(torch.uint32)
+        kb = [keys.clone() for _ in range(steps)]
+        vb = [vals.clone() for _ in range(steps)]
+        with Timer(torch) as t:
+            for k in range(steps):
+                im.inplace_merge_kv(kb[k], vb[k], la)
+        wk, wv = oracle.merge_kv(keys.cpu().numpy(), vals.cpu().numpy(), la)
+        bad = mismatches(kb[0], wk) + mismatches(vb[0], wv)
+        n = la + lb
+        ms = t.ms / steps
+        return {"workload": "int64 keys in [0,4096) + uint32 payload, 2^26+2^26",
+                "gelem_s": round(n / ms / 1e6, 2), "ms": round(ms, 4), "mismatches": bad,
+                "effective_gb_s": round(2 * 12 * n / ms / 1e6, 1)}
+    if name == "c2_skew":
+        la, lb, hi = 2 ** 23, 2 ** 27 - 2 ** 23, 2 ** 31
+    else:
+        la, lb, hi = 2 ** 27, 2 ** 27, 1024
+    pristine = gen.torch_pair_uniform(la, lb, SEED + (21 if name == "c2_skew" else 22), dev, hi=hi)
+    ms, _, bufs = timed_merges(torch, im, pristine, la, steps, 1)
+    want = oracle.merge(pristine.cpu().numpy(), la)
+    bad = mismatches(bufs[0], want)
+    n = la + lb
+    return {"workload": "int32 %d+%d keys in [0,%d)" % (la, lb, hi), "gelem_s": round(n / ms / 1e6, 2),
+            "ms": round(ms, 4), "mismatches": bad}
+
+
+def bench_batched(torch, im, oracle, gen, dev, steps):
+    log("c4: generating 4096 instances")
+    data, off_d, off = gen.torch_batch(4096, SEED + 40, dev)
+    total = int(off[-1])
+    max_inst = int(np.max(off[2::2] - off[0:-1:2]))
+    fn = lambda b: im.batched_inplace_merge(b, off_d, max_instance=max_inst)
+    ms_b, _, bufs = timed_merges(torch, im, data, 0, steps, 1, fn=fn)
+    # the same 4096 instances as separate plain calls on one stream
+    loop_buf = data.clone()
+
+    def plain_loop(b):
+        for q in range(4096):
+            o0, o1, o2 = int(off[2 * q]), int(off[2 * q + 1]), int(off[2 * q + 2])
+            im.inplace_merge(b[o0:o2], o1 - o0)
+    plain_loop(data.clone())        # warm
+    with Timer(torch) as t:
+        plain_loop(loop_buf)
+    ms_p = t.ms
+    host = data.cpu().numpy()
+    got_b = bufs[0].cpu().numpy()
+    got_p = loop_buf.cpu().numpy()
+    bad_b = bad_p = 0
+    for q in range(4096):
+        o0, o1, o2 = off[2 * q], off[2 * q + 1], off[2 * q + 2]
+        want = oracle.merge(host[o0:o2], int(o1 - o0))
+        bad_b += int(np.count_nonzero(got_b[o0:o2] != want))
+        bad_p += int(np.count_nonzero(got_p[o0:o2] != want))
+    log("c4: batched %.3f ms, plain loop %.3f ms" % (ms_b, ms_p))
+    return {"workload": "4096 instances, L_A, L_B ~ round(2^U[6,20]) int32, %d elements" % total,
+            "batched_gelem_s": round(total / ms_b / 1e6, 2), "batched_ms": round(ms_b, 4),
+            "plain_loop_gelem_s": round(total / ms_p / 1e6, 2), "plain_loop_ms": round(ms_p, 3),
+            "speedup_vs_plain_loop": round(ms_p / ms_b, 2),
+            "mismatches_batched": bad_b, "mismatches_plain_loop": bad_p}
+
+
+def bench_sort(torch, im, oracle, gen, dev):
+    n = 2 ** 28
+    log("c4: merge sort of 2^28 int32")
+    x = gen.torch_unsorted(n, SEED + 41, dev)
+    ms, _, bufs = timed_merges(torch, im, x, 0, 2, 1, fn=lambda b: im.inplace_merge_sort(b))
+    want = oracle.sort_keys(x.cpu().numpy())
+    bad = mismatches(bufs[0], want)
+    return {"workload": "in-place merge sort, 2^28 int32 uniform", "gelem_s": round(n / ms / 1e6, 3),
+            "ms": round(ms, 3), "mismatches": bad}
+
+
+def bench_learned(torch, im, oracle, gen, dev, steps):
+    la = lb = 2 ** 28
+    n = la + lb
+    log("c5: generating int64 lognormal | 16-component mixture, 2^28 + 2^28")
+    pristine = gen.torch_pair_learned(la, lb, SEED + 50, dev)
+    model = im.MergeModel(seed=SEED)
+    t0 = time.perf_counter()
+    model.train(pristine, la, samples=8192, steps=1500, lr=3e-3)
+    train_s = time.perf_counter() - t0
+    k = min(steps, 4)
+    ms_l, prof_l, bufs = timed_merges(torch, im, pristine, la, k, 1,
+                                      fn=lambda b: model.merge(b, la), profile=True)
+    st_l = im.fetch_stats()
+    want = oracle.merge(pristine.cpu().numpy(), la)
+    bad_l = mismatches(bufs[0], want)
+    del bufs
+    ms_p, prof_p, bufs = timed_merges(torch, im, pristine, la, k, 1, profile=True)
+    st_p = im.fetch_stats()
+    bad_p = mismatches(bufs[0], want)
+    del bufs
+    # probes per diagonal on the tile diagonals of this workload
+    ks = torch.linspace(0, n, 65537, device=dev).to(torch.int64)
+    _, probes_l = model.corank(pristine, la, ks)
+    _, probes_p = im.corank(pristine, la, ks, probes=True)
+    log("c5: learned %.3f ms, plain %.3f ms" % (ms_l, ms_p))
+    search_ms = lambda p: (p["split"][0] + p["tilerank"][0]) / k
+    return {"workload": "int64, A lognormal(20,2), B 16-comp. mixture, 2^28+2^28",
+            "learned_gelem_s": round(n / ms_l / 1e6, 2), "plain_gelem_s": round(n / ms_p / 1e6, 2),
+            "learned_ms": round(ms_l, 4), "plain_ms": round(ms_p, 4),
+            "search_ms_learned": round(search_ms(prof_l), 4),
+            "search_ms_plain": round(search_ms(prof_p), 4),
+            "probes_per_search_learned": round(st_l["search_probes"] / max(st_l["searches"], 1), 2),
+            "probes_per_search_plain": round(st_p["search_probes"] / max(st_p["searches"], 1), 2),
+            "probes_per_diagonal_learned_65537": round(float(probes_l.double().mean()), 2),
+            "probes_per_diagonal_plain_65537": round(float(probes_p.double().mean()), 2),
+            "train_s": round(train_s, 3), "mismatches_learned": bad_l, "mismatches_plain": bad_p}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--forms", choices=["all", "none"], default="all")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU (the merge is measured on one "
+              "MI355X); --gpus %d / WORLD_SIZE=%d is not supported" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gen
+    import paper_2005_12648_amd as im
+    import oracle
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    im.load()
+    dev = torch.device("cuda:0")
+
+    head = bench_headline(torch, im, oracle, gen, dev, args)
+    n = head["n"]
+    value = n / head["ms"] / 1e6
+    roof = roofline(head["prof"], head["stats"], 4, args.steps, "c2")
+    forms = {}
+    if args.forms == "all":
+        for name in ("c2_skew", "c2_dup", "c3_kv"):
+            log("variant", name)
+            forms[name] = bench_variant(torch, im, oracle, gen, dev, name, 3)
+            torch.cuda.empty_cache()
+        forms["c4_batched"] = bench_batched(torch, im, oracle, gen, dev, 3)
+        torch.cuda.empty_cache()
+        forms["c4_sort"] = bench_sort(torch, im, oracle, gen, dev)
+        torch.cuda.empty_cache()
+        forms["c5_learned"] = bench_learned(torch, im, oracle, gen, dev, args.steps)
+    st = head["stats"]
+    line = {
+        "metric": "Gelem/s, in-place merge of int32 L_A=L_B=2^27",
+        "value": round(value, 3),
+        "unit": "Gelem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded, generated on the device)",
+        "config": {"workload": "c2: int32 in-place merge, L_A=L_B=2^27, runs uniform in [0,2^31) "
+                               "each sorted", "elements": n,
+                   "levels_used": st["levels_used"], "leaves": st["leaves"],
+                   "leaf_capacity": st["leaf_capacity"], "tile": st["tile"]},
+        "effective_hbm_gb_s": round(2 * 4 * n / head["ms"] / 1e6, 1),
+        "effective_hbm_frac": round(2 * 4 * n / head["ms"] / 1e6 / HBM_PEAK_GBS, 4),
+        "mismatches": head.get("mismatch"),
+        "roofline": roof,
+        "cpu_baseline": head["cpu"],
+        "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,3 +140,71 @@ def make(name: str, scale: int = 0):
         la, lb = max(c["la"] // d, 1), max(c["lb"] // d, 1)
         return pair_learned(la, lb, c["seed"]), la
     raise KeyError(name)
+
+
+# --------------------------------------------------------------------------
+# Device-side generators (same distributions, drawn with torch's seeded
+# generator on the GPU so full-size benchmark inputs take milliseconds).
+# Values differ from the numpy draws above; both are seeded and synthetic.
+# --------------------------------------------------------------------------
+def _tgen(seed: int, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return g
+
+
+def torch_sorted_uniform(n: int, hi: int, seed: int, device, dtype=None):
+    import torch
+    dtype = dtype or torch.int32
+    g = _tgen(seed, device)
+    x = torch.randint(0, hi, (n,), generator=g, device=device, dtype=torch.int64)
+    return torch.sort(x.to(dtype)).values
+
+
+def torch_pair_uniform(la: int, lb: int, seed: int, device, hi: int = 2 ** 31, dtype=None):
+    import torch
+    a = torch_sorted_uniform(la, hi, seed, device, dtype)
+    b = torch_sorted_uniform(lb, hi, seed + 1_000_003, device, dtype)
+    return torch.cat([a, b])
+
+
+def torch_unsorted(n: int, seed: int, device, dtype=None):
+    import torch
+    g = _tgen(seed, device)
+    return torch.randint(0, 2 ** 31, (n,), generator=g, device=device,
+                         dtype=torch.int64).to(dtype or torch.int32)
+
+
+def torch_batch(n_inst: int, seed: int, device, lo_exp: float = 6.0, hi_exp: float = 20.0):
+    """Packed int32 instances (each run sorted) and int64 offsets[2n+1], on device."""
+    import torch
+    r = _rng(seed)
+    la = np.rint(2.0 ** r.uniform(lo_exp, hi_exp, size=n_inst)).astype(np.int64)
+    lb = np.rint(2.0 ** r.uniform(lo_exp, hi_exp, size=n_inst)).astype(np.int64)
+    off = np.zeros(2 * n_inst + 1, dtype=np.int64)
+    off[1::2] = la
+    off[2::2] = lb
+    off = np.cumsum(off)
+    total = int(off[-1])
+    g = _tgen(seed + 1, device)
+    vals = torch.randint(0, 2 ** 31, (total,), generator=g, device=device, dtype=torch.int64)
+    # sort every run at once: run index in the high bits, value in the low 31
+    run_len = torch.from_numpy(np.diff(off)).to(device)
+    run_id = torch.repeat_interleave(torch.arange(2 * n_inst, device=device), run_len)
+    key = torch.sort((run_id << 31) | vals).values
+    data = (key & (2 ** 31 - 1)).to(torch.int32)
+    return data, torch.from_numpy(off).to(device), off
+
+
+def torch_pair_learned(la: int, lb: int, seed: int, device):
+    import torch
+    g = _tgen(seed, device)
+    a = torch.empty(la, dtype=torch.float64, device=device).log_normal_(20.0, 2.0, generator=g)
+    r = _rng(seed)
+    means = torch.from_numpy(r.uniform(0.0, 2.0 ** 40, size=16)).to(device)
+    comp = torch.randint(0, 16, (lb,), generator=g, device=device)
+    b = torch.normal(means[comp], 2.0 ** 30, generator=g)
+    a = torch.floor(torch.clamp(a, 0, 2.0 ** 62)).to(torch.int64)
+    b = torch.floor(torch.clamp(b, 0, 2.0 ** 62)).to(torch.int64)
+    return torch.cat([torch.sort(a).values, torch.sort(b).values])

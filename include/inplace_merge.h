@@ -78,6 +78,8 @@ typedef struct {
     int64_t tiles;           /* workgroup tiles in the pair merge (device)    */
     int64_t rotations;       /* partition exchanges performed (device)        */
     int64_t rotated_elems;   /* elements moved by partition exchanges (dev.)  */
+    int64_t reversed_elems;  /* of which by three-reversal exchanges (dev.)   */
+    int64_t leaf_elems;      /* elements merged by the leaf merge (device)    */
     int64_t search_probes;   /* key-pair probes in all split searches (dev.)  */
     int64_t searches;        /* split searches performed (device)             */
 } im_stats;
@@ -144,6 +146,15 @@ const char *inplace_merge_last_error(void);
  * Synchronises `stream` to read the device counters. */
 int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream);
 
+/* Stage timing for the calling thread.  While enabled, every merge records
+ * HIP events on its stream around its launch groups; _read synchronises
+ * `stream`, adds the elapsed milliseconds per stage into ms[0..nstages)
+ * (0: split searches, 1: partition exchanges, 2: leaf planning, 3: tile
+ * co-ranks, 4: leaf merge), the number of kernel launches into launches[]
+ * (may be NULL), and forgets the recorded events. */
+int inplace_merge_profile(int enable);
+int inplace_merge_profile_read(double *ms, int64_t *launches, int nstages, hipStream_t stream);
+
 /* ---------------------------------------------------------------------- */
 /* Stage entry points (used by the unit parity tests and the benchmark).   */
 /* ---------------------------------------------------------------------- */
@@ -151,9 +162,12 @@ int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream);
 /* Co-rank (Sec. 3.1, the exact "optimal" split for any output rank): for
  * each diagonal d_k[p] in [0, L_A+L_B], d_out[p] = number of A elements among
  * the first d_k[p] outputs of the stable merge of data[0,L_A) and
- * data[L_A,L_A+L_B).  One wavefront lane per diagonal.  All device pointers. */
+ * data[L_A,L_A+L_B) (a diagonal outside that range gives -1).  One wavefront
+ * lane per diagonal, binary search.  d_probes (may be NULL) receives the key
+ * pairs compared per diagonal.  All device pointers. */
 int im_corank(const void *data, int64_t L_A, int64_t L_B, int dtype,
-              const int64_t *d_k, int64_t nk, int64_t *d_out, hipStream_t stream);
+              const int64_t *d_k, int64_t nk, int64_t *d_out, int32_t *d_probes,
+              hipStream_t stream);
 
 /* Partition exchange (Sec. 3.4): data[0, lx+ly) = X|Y becomes Y|X.  Equal
  * sizes use one block swap (one linear-shifting step); otherwise the

@@ -24,7 +24,7 @@ __all__ = [
     "IMError", "library_path", "load", "inplace_merge", "inplace_merge_kv",
     "batched_inplace_merge", "batched_inplace_merge_kv", "inplace_merge_sort",
     "corank", "rotate", "fetch_stats", "workspace_bytes", "set_workspace",
-    "MergeModel", "MLP_HIDDEN", "MLP_PARAMS",
+    "MergeModel", "MLP_HIDDEN", "MLP_PARAMS", "profile", "profile_read", "STAGES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -58,6 +58,7 @@ class _Stats(ctypes.Structure):
         ("max_levels", ctypes.c_int32), ("levels_used", ctypes.c_int32),
         ("leaves", ctypes.c_int64), ("tiles", ctypes.c_int64),
         ("rotations", ctypes.c_int64), ("rotated_elems", ctypes.c_int64),
+        ("reversed_elems", ctypes.c_int64), ("leaf_elems", ctypes.c_int64),
         ("search_probes", ctypes.c_int64), ("searches", ctypes.c_int64),
     ]
 
@@ -90,7 +91,7 @@ def load():
         "inplace_merge_sort": [vp, i64, c_int, vp],
         "inplace_merge_set_workspace": [vp, ctypes.c_size_t],
         "inplace_merge_fetch_stats": [ctypes.POINTER(_Stats), vp],
-        "im_corank": [vp, i64, i64, c_int, vp, i64, vp, vp],
+        "im_corank": [vp, i64, i64, c_int, vp, i64, vp, vp, vp],
         "im_rotate": [vp, i64, i64, c_int, vp],
         "merge_model_create": [ctypes.POINTER(vp), vp, ctypes.c_uint64],
         "merge_model_train": [vp, vp, i64, i64, c_int, ctypes.POINTER(_TrainCfg), vp],
@@ -103,6 +104,8 @@ def load():
         "merge_model_save": [vp, ctypes.c_char_p],
         "merge_model_load": [ctypes.POINTER(vp), ctypes.c_char_p],
         "merge_model_free": [vp],
+        "inplace_merge_profile": [c_int],
+        "inplace_merge_profile_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), c_int, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -212,19 +215,24 @@ def inplace_merge_sort(data: torch.Tensor, stream=None) -> torch.Tensor:
     return data
 
 
-def corank(data: torch.Tensor, la: int, ks: torch.Tensor, stream=None) -> torch.Tensor:
-    """Co-rank i(k) of each diagonal in ks (device int64) for runs data[:la], data[la:]."""
+def corank(data: torch.Tensor, la: int, ks: torch.Tensor, stream=None, probes: bool = False):
+    """Co-rank i(k) of each diagonal in ks (device int64) for runs data[:la], data[la:].
+
+    With probes=True also returns the key pairs compared per diagonal (int32)."""
     _dev_tensor(data, "data")
     _dev_tensor(ks, "ks")
     if ks.dtype != torch.int64:
         raise TypeError("ks must be int64")
     out = torch.empty_like(ks)
+    pr = torch.empty(ks.numel(), dtype=torch.int32, device=ks.device) if probes else None
     n = data.numel()
     with torch.cuda.device(data.device):
         _check(load().im_corank(ctypes.c_void_p(data.data_ptr()), la, n - la, _key_code(data),
                                 ctypes.c_void_p(ks.data_ptr()), ks.numel(),
-                                ctypes.c_void_p(out.data_ptr()), _stream(stream)))
-    return out
+                                ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(pr.data_ptr()) if probes else None,
+                                _stream(stream)))
+    return (out, pr) if probes else out
 
 
 def rotate(data: torch.Tensor, lx: int, stream=None) -> torch.Tensor:
@@ -244,6 +252,22 @@ def fetch_stats(stream=None) -> dict:
     st = _Stats()
     _check(load().inplace_merge_fetch_stats(ctypes.byref(st), _stream(stream)))
     return {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+
+STAGES = ("split", "rotate", "plan", "tilerank", "leafmerge")
+
+
+def profile(enable: bool):
+    """Record per-stage HIP events on the merge's stream (this thread)."""
+    _check(load().inplace_merge_profile(1 if enable else 0))
+
+
+def profile_read(stream=None) -> dict:
+    """{stage: (ms, launches)} accumulated since the last read (synchronises)."""
+    ms = (ctypes.c_double * len(STAGES))()
+    ln = (ctypes.c_int64 * len(STAGES))()
+    _check(load().inplace_merge_profile_read(ms, ln, len(STAGES), _stream(stream)))
+    return {s: (ms[i], ln[i]) for i, s in enumerate(STAGES)}
 
 
 def workspace_bytes(total_elems: int, n_inst: int, dtype: torch.dtype) -> int:

@@ -22,6 +22,45 @@ thread_local std::string g_err = "";
 thread_local im_stats g_stats = {};
 thread_local Counters *g_last_ctr = nullptr;
 
+// Stage timing (inplace_merge_profile): events recorded on the caller's
+// stream around each group of launches, read back by
+// inplace_merge_profile_read.
+enum { kStSplit = 0, kStRotate = 1, kStPlan = 2, kStTileRank = 3, kStLeafMerge = 4, kStCount = 5 };
+struct ProfRec {
+    int stage;
+    int launches;
+    hipEvent_t a, b;
+};
+thread_local bool g_prof = false;
+thread_local std::vector<ProfRec> g_prof_recs;
+thread_local std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Returns the start event (or nullptr when profiling is off).
+hipEvent_t prof_begin(hipStream_t s) {
+    if (!g_prof) return nullptr;
+    hipEvent_t a = prof_event();
+    if (a && hipEventRecord(a, s) != hipSuccess) return nullptr;
+    return a;
+}
+
+void prof_end(hipEvent_t a, int stage, int launches, hipStream_t s) {
+    if (!a) return;
+    hipEvent_t b = prof_event();
+    if (!b || hipEventRecord(b, s) != hipSuccess) return;
+    g_prof_recs.push_back(ProfRec{stage, launches, a, b});
+}
+
 int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
@@ -230,14 +269,25 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         if (bits & kErrOffsets) return fail(IM_ERR_INVALID_ARG, "offsets are not monotone");
         if (bits & kErrNotSorted) return fail(IM_ERR_NOT_SORTED, "an input run is not ascending");
     }
+    const bool prof = g_prof && !stream_capturing(s);
     for (int lv = 0; lv < pl.max_levels; ++lv) {
+        hipEvent_t e0 = prof ? prof_begin(s) : nullptr;
         IM_HIP(launch_split(key_dt, keys, offs, pl, w, lv, mlp, s), "launch split");
+        prof_end(e0, kStSplit, 1, s);
+        hipEvent_t e1 = prof ? prof_begin(s) : nullptr;
         IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 0, s), "launch rotate A");
         IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");
+        prof_end(e1, kStRotate, 2, s);
     }
+    hipEvent_t e2 = prof ? prof_begin(s) : nullptr;
     IM_HIP(launch_plan(pl, w, s), "launch plan");
+    prof_end(e2, kStPlan, 1, s);
+    hipEvent_t e3 = prof ? prof_begin(s) : nullptr;
     IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
+    prof_end(e3, kStTileRank, 1, s);
+    hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
     IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
+    prof_end(e4, kStLeafMerge, 1, s);
     rc = ws_leave(ds, s);
     if (rc) return rc;
 
@@ -423,20 +473,47 @@ int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream) {
     for (int l = 0; l < kMaxLevels; ++l) nrot += (int64_t)(c.level_rot[l] >> kRotCountShift);
     out->rotations = nrot;
     out->rotated_elems = (int64_t)c.rotated;
+    out->reversed_elems = (int64_t)c.rotated_rev;
+    out->leaf_elems = (int64_t)c.leaf_elems;
     out->search_probes = (int64_t)c.probes;
     out->searches = (int64_t)c.searches;
     if (c.error) return fail(IM_ERR_DEVICE, "device error bits " + std::to_string(c.error));
     return IM_OK;
 }
 
+int inplace_merge_profile(int enable) {
+    g_prof = enable != 0;
+    return IM_OK;
+}
+
+int inplace_merge_profile_read(double *ms, int64_t *launches, int nstages, hipStream_t stream) {
+    if (!ms || nstages < 0) return fail(IM_ERR_INVALID_ARG, "null output");
+    for (int i = 0; i < nstages; ++i) {
+        ms[i] = 0.0;
+        if (launches) launches[i] = 0;
+    }
+    if (!g_prof_recs.empty()) IM_HIP(hipStreamSynchronize(stream), "synchronise for profile");
+    for (const ProfRec &r : g_prof_recs) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && r.stage < nstages) {
+            ms[r.stage] += t;
+            if (launches) launches[r.stage] += r.launches;
+        }
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_recs.clear();
+    return IM_OK;
+}
+
 int im_corank(const void *data, int64_t L_A, int64_t L_B, int dtype, const int64_t *d_k,
-              int64_t nk, int64_t *d_out, hipStream_t stream) {
+              int64_t nk, int64_t *d_out, int32_t *d_probes, hipStream_t stream) {
     int rc = check_common(data, L_A, L_B, dtype);
     if (rc) return rc;
     if (nk < 0) return fail(IM_ERR_INVALID_ARG, "negative count");
     if (nk == 0) return IM_OK;
     if (!d_k || !d_out) return fail(IM_ERR_INVALID_ARG, "null pointer");
-    IM_HIP(launch_corank(dtype, data, L_A, L_B, d_k, nk, d_out, nullptr, nullptr, stream),
+    IM_HIP(launch_corank(dtype, data, L_A, L_B, d_k, nk, d_out, nullptr, d_probes, stream),
            "launch co-rank");
     return IM_OK;
 }

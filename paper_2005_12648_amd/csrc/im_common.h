@@ -58,6 +58,8 @@ struct Counters {
     unsigned long long leaves;
     unsigned long long tiles;
     unsigned long long rotated;       // elements moved by exchanges
+    unsigned long long rotated_rev;   // of which in three-reversal exchanges
+    unsigned long long leaf_elems;    // elements of all leaves (merged in LDS)
     unsigned long long probes;        // key-pair probes of split searches
     unsigned long long searches;      // split searches
     unsigned long long levels_used;   // max level index that had nodes, +1

@@ -158,13 +158,16 @@ __global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *
         __syncthreads();
 
         // 4. leaf barrier (only leaves with several tiles)
+        // The counter is touched only with relaxed device-scope atomics: the
+        // tile's loads have returned (their values are in LDS), and an
+        // acquire/release fence at device scope would write back or
+        // invalidate the whole L2 of this XCD on every poll.
         if (lf.ntiles > 1) {
             if (tid == 0) {
-                __threadfence();
-                atomicAdd(&w.arrive[l], 1u);
+                __hip_atomic_fetch_add(&w.arrive[l], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 unsigned spins = 0;
                 int ok = 1;
-                while (__hip_atomic_load(&w.arrive[l], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                while (__hip_atomic_load(&w.arrive[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                        (unsigned)lf.ntiles) {
                     __builtin_amdgcn_s_sleep(2);
                     if (++spins > kSpinLimit) {
@@ -209,16 +212,19 @@ constexpr int kPlanThreads = 1024;
 __global__ __launch_bounds__(kPlanThreads) void k_plan(Plan pl, Work w) {
     __shared__ long long buf[kPlanThreads];
     __shared__ long long s_run;
+    __shared__ unsigned long long s_elems;
     int64_t L = (int64_t)w.ctr->leaves;
     if (L > pl.cap_leaves) L = pl.cap_leaves;
     const int tid = threadIdx.x;
-    if (tid == 0) s_run = 0;
+    unsigned long long my_elems = 0;
+    if (tid == 0) { s_run = 0; s_elems = 0; }
     __syncthreads();
     for (int64_t base = 0; base < L; base += kPlanThreads) {
         int64_t l = base + tid;
         long long c = 0;
         if (l < L) {
             int64_t S = w.leaves[l].la + w.leaves[l].lb;
+            my_elems += (unsigned long long)S;
             c = (S + pl.tile - 1) / pl.tile;
             w.leaves[l].ntiles = (int32_t)c;
             w.arrive[l] = 0u;
@@ -238,7 +244,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Plan pl, Work w) {
         if (tid == kPlanThreads - 1) s_run = run + buf[tid];
         __syncthreads();
     }
+    if (my_elems) atomicAdd(&s_elems, my_elems);
+    __syncthreads();
     if (tid == 0) {
+        w.ctr->leaf_elems = s_elems;
         long long tot = s_run;
         if (tot > pl.cap_tiles) {
             atomicOr(&w.ctr->error, kErrCapacity);

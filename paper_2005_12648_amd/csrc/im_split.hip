@@ -83,6 +83,7 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
     r.nw = nw;
     w.rot[slot] = r;
     atomicAdd(&w.ctr->rotated, (unsigned long long)(lx + ly));
+    if (lx != ly) atomicAdd(&w.ctr->rotated_rev, (unsigned long long)(lx + ly));
 }
 
 __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const Node &nd) {

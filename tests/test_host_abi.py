@@ -62,7 +62,7 @@ def test_validation_codes_without_device_work():
     assert lib.batched_inplace_merge(fake, fake, -5, 100, 0, 0, None) == -1
     assert lib.inplace_merge_sort(fake, -3, 0, None) == -1
     assert lib.im_rotate(fake, 3, 4, 3, None) == -2
-    assert lib.im_corank(fake, 3, 3, 0, None, 5, None, None) == -1
+    assert lib.im_corank(fake, 3, 3, 0, None, 5, None, None, None) == -1
     # empty work is a successful no-op that touches nothing
     assert lib.inplace_merge(None, 0, 0, 0, None) == 0
     assert lib.inplace_merge(fake, 0, 7, 0, None) == 0
