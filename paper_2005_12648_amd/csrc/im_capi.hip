@@ -95,6 +95,11 @@ struct DevState {
     int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // leaf grid by (key 4/8, payload 0/4/8)
     int64_t *sort_off = nullptr; // offsets of the merge-sort passes
     int64_t sort_off_cap = 0;
+    // Tile flags sit right after the counters.  flag_cap flags there are
+    // known to hold only values < epoch (zeroed, or written by earlier
+    // calls); the rest of the layout always starts after them.
+    int64_t flag_cap = 0;
+    uint32_t epoch = 0;
 };
 
 DevState g_dev[64];
@@ -148,7 +153,7 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     return true;
 }
 
-size_t carve(const Plan &pl, void *base, Work *w) {
+size_t carve(const Plan &pl, int64_t flag_slots, void *base, Work *w) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> void * {
         void *p = base ? (char *)base + off : nullptr;
@@ -157,14 +162,15 @@ size_t carve(const Plan &pl, void *base, Work *w) {
     };
     Work x;
     x.ctr = (Counters *)take(sizeof(Counters));
+    x.tile_flag = (unsigned *)take(sizeof(unsigned) * std::max<int64_t>(flag_slots, pl.cap_tiles));
     x.nodes[0] = (Node *)take(sizeof(Node) * pl.cap_nodes);
     x.nodes[1] = (Node *)take(sizeof(Node) * pl.cap_nodes);
     x.rot = (Rot *)take(sizeof(Rot) * pl.cap_rot);
     x.leaves = (Leaf *)take(sizeof(Leaf) * pl.cap_leaves);
     x.tile_start = (int64_t *)take(sizeof(int64_t) * pl.cap_leaves);
-    x.arrive = (unsigned *)take(sizeof(unsigned) * pl.cap_leaves);
     x.tile_rank = (int64_t *)take(sizeof(int64_t) * pl.cap_tiles);
     x.tile_leaf = (int32_t *)take(sizeof(int32_t) * pl.cap_tiles);
+    x.tile_dep = (int32_t *)take(sizeof(int32_t) * 2 * pl.cap_tiles);
     x.offsets1 = (int64_t *)take(sizeof(int64_t) * 4);
     if (w) *w = x;
     return off;
@@ -197,6 +203,7 @@ int acquire_ws(DevState *ds, size_t need, void **out) {
                                               " bytes failed");
         }
         ds->ws_bytes = bytes;
+        ds->flag_cap = 0;          // new memory: no flag is known to be clear
     }
     *out = ds->ws;
     return IM_OK;
@@ -247,14 +254,30 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     Plan pl;
     if (!make_plan(ds, ek, ev, n_inst, total, max_inst, &pl))
         return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
-    size_t need = carve(pl, nullptr, nullptr);
+    size_t need = carve(pl, ds->flag_cap, nullptr, nullptr);
     void *base = nullptr;
     int rc = acquire_ws(ds, need, &base);
     if (rc) return rc;
+    if (carve(pl, ds->flag_cap, nullptr, nullptr) > need) {
+        // the buffer was replaced (flag_cap reset): size again
+        need = carve(pl, ds->flag_cap, nullptr, nullptr);
+        rc = acquire_ws(ds, need, &base);
+        if (rc) return rc;
+    }
     Work w;
-    carve(pl, base, &w);
+    carve(pl, ds->flag_cap, base, &w);
     rc = ws_enter(ds, s);
     if (rc) return rc;
+    // Tile flags: a tile is "read" when its flag equals this call's epoch.
+    // Flags beyond flag_cap may hold stale data of other arrays, so they are
+    // cleared (with a kernel: graph-capture safe) before first use.
+    if (pl.cap_tiles > ds->flag_cap || ds->epoch == 0xFFFFFFFFu) {
+        int64_t nflags = std::max<int64_t>(ds->flag_cap, pl.cap_tiles);
+        IM_HIP(launch_fill32(w.tile_flag, nflags, 0u, s), "clear tile flags");
+        ds->flag_cap = nflags;
+        if (ds->epoch == 0xFFFFFFFFu) ds->epoch = 0;
+    }
+    pl.epoch = ++ds->epoch;
 
     const bool check = checked_mode();
     if (std::getenv("IM_FAULT") && std::strcmp(std::getenv("IM_FAULT"), "launch") == 0)
@@ -284,7 +307,8 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     prof_end(e2, kStPlan, 1, s);
     hipEvent_t e3 = prof ? prof_begin(s) : nullptr;
     IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
-    prof_end(e3, kStTileRank, 1, s);
+    IM_HIP(launch_tiledeps(pl, w, s), "launch tile dependencies");
+    prof_end(e3, kStTileRank, 2, s);
     hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
     IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
     prof_end(e4, kStLeafMerge, 1, s);
@@ -440,12 +464,12 @@ size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dt
     if (!make_plan(ds, key_size(dtype), 8, std::max<int64_t>(n_inst, 1), std::max<int64_t>(total_elems, 1),
                    0, &pl))
         return 0;
-    size_t a = carve(pl, nullptr, nullptr);
+    size_t a = carve(pl, 0, nullptr, nullptr);
     Plan pl2;
     if (!make_plan(ds, key_size(dtype), 0, std::max<int64_t>(n_inst, 1),
                    std::max<int64_t>(total_elems, 1), 0, &pl2))
         return 0;
-    return std::max(a, carve(pl2, nullptr, nullptr));
+    return std::max(a, carve(pl2, 0, nullptr, nullptr));
 }
 
 int inplace_merge_set_workspace(void *d_ws, size_t bytes) {
@@ -455,6 +479,7 @@ int inplace_merge_set_workspace(void *d_ws, size_t bytes) {
     if (d_ws != nullptr && bytes < 4096) return fail(IM_ERR_WORKSPACE, "workspace too small");
     ds->user_ws = d_ws;
     ds->user_bytes = d_ws ? bytes : 0;
+    ds->flag_cap = 0;              // a different buffer: no flag is known clear
     g_err.clear();
     return IM_OK;
 }

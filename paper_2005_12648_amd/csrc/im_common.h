@@ -93,6 +93,8 @@ struct Plan {
     int32_t max_levels;     // division levels enqueued
     int32_t grid_leaf;      // persistent grid of the leaf merge
     int64_t cap_nodes, cap_rot, cap_leaves, cap_tiles;
+    uint32_t epoch;         // value a tile writes to its "inputs read" flag
+    uint32_t pad;
 };
 
 // Workspace carve-up (device pointers).
@@ -104,7 +106,8 @@ struct Work {
     int64_t *tile_start;     // per leaf: first tile index (exclusive scan)
     int64_t *tile_rank;      // per tile: co-rank at the tile's first diagonal
     int32_t *tile_leaf;      // per tile: its leaf
-    unsigned int *arrive;    // per leaf: arrival counter of the leaf barrier
+    int32_t *tile_dep;       // per tile: [lo, hi] leaf-local tiles reading its window
+    unsigned int *tile_flag; // per tile: == epoch once its inputs are in LDS
     int64_t *offsets1;       // [3] offsets of a single-instance call
 };
 
@@ -123,6 +126,8 @@ hipError_t launch_tilerank(int key, void *data, const int64_t *d_offsets, const 
                            const Work &w, const MlpDev *mlp, hipStream_t s);
 hipError_t launch_leafmerge(int key, int esize_v, void *keys, void *vals, const Plan &pl,
                             const Work &w, hipStream_t s);
+hipError_t launch_tiledeps(const Plan &pl, const Work &w, hipStream_t s);
+hipError_t launch_fill32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 // Tile geometry of the leaf merge for a (key size, payload size) pair.
 void leaf_geometry(int esize_k, int esize_v, int *threads, int *ipt, size_t *lds_bytes);
 int leaf_grid(int esize_k, int esize_v);   // persistent grid (resident workgroups)

@@ -9,16 +9,21 @@
 //   2. every thread finds its own sub-diagonal by a co-rank search in LDS and
 //      merges `ipt` outputs into registers (stable: ties take A);
 //   3. outputs go back to LDS (padded to avoid bank conflicts);
-//   4. leaf barrier: the tile's output window overlaps input slices that
-//      other tiles of the same leaf read, so every tile of the leaf first
-//      reports "inputs read" on the leaf's arrival counter and waits for all
-//      of them;
+//   4. wait: the tile's output window overlaps input slices of other tiles
+//      of the same leaf.  Every tile publishes "inputs read" in its own flag
+//      as soon as its slices are in LDS; before storing, a tile waits for
+//      the flags of exactly the tiles that read its window (k_tiledeps
+//      computes that range from the co-ranks: A elements only move right,
+//      B elements only move left, so the readers form one contiguous range
+//      of tiles around the tile itself);
 //   5. coalesced store of the window.
 // The grid is persistent and co-resident (cooperative launch); tile t is
 // handled by workgroup t mod G in increasing t, and a leaf has at most G
-// tiles, so the leaf holding the smallest unfinished tile always has all of
-// its tiles running -- the waits cannot deadlock.  The wait is bounded: on
-// expiry the workgroup raises an error bit and skips its store.
+// tiles, so every tile a waiting tile depends on is either done or held by a
+// workgroup that has finished all its earlier tiles -- the smallest
+// unfinished tile always makes progress and the waits cannot deadlock.  The
+// wait is bounded: on expiry the workgroup raises an error bit and skips its
+// store.
 #include <type_traits>
 #include "im_common.h"
 
@@ -31,8 +36,64 @@ constexpr unsigned kSpinLimit = 1u << 26;
 template <int T>
 struct LdsPad { static constexpr int elems = T + T / 32 + 1; };
 
+// Geometry of one tile: its leaf, output window [d0, d0+n) inside the leaf,
+// and where its A-slice (na elements) and B-slice (n - na) start.
+struct TileGeo {
+    int64_t base, d0, tbase;
+    int n, na, a_off, b_off;
+    int32_t leaf, ntiles, local, wlo, whi;
+};
+
+__device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t t, int T) {
+    TileGeo g;
+    const int32_t l = w.tile_leaf[t];
+    const Leaf lf = w.leaves[l];
+    const int64_t local = t - w.tile_start[l];
+    const int64_t S = lf.la + lf.lb;
+    const int64_t d0 = local * (int64_t)T;
+    const int64_t d1 = d0 + T < S ? d0 + T : S;
+    const int n = (int)(d1 - d0);
+    const int64_t ia0 = w.tile_rank[t];
+    const int64_t ia1 = (local + 1 < lf.ntiles) ? w.tile_rank[t + 1] : lf.la;
+    // For ascending runs na = ia1 - ia0 already lies in this interval; the
+    // clamp only keeps every access inside the leaf when a caller passes
+    // unsorted runs (then the result is an unspecified permutation).
+    int64_t na64 = ia1 - ia0;
+    const int64_t na_lo = (d1 - lf.lb - ia0) > 0 ? (d1 - lf.lb - ia0) : 0;
+    const int64_t na_hi = (lf.la - ia0) < (int64_t)n ? (lf.la - ia0) : (int64_t)n;
+    if (na64 < na_lo) na64 = na_lo;
+    if (na64 > na_hi) na64 = na_hi;
+    g.base = lf.base;
+    g.d0 = d0;
+    g.n = n;
+    g.na = (int)na64;
+    // Offsets relative to the leaf start (a leaf is far below 2^31
+    // elements): every address is a uniform base plus one 32-bit offset.
+    g.a_off = (int)ia0;                                   // A-slice start
+    g.b_off = (int)(lf.la + (d0 - ia0)) - g.na;           // B-slice start, minus na
+    g.leaf = l;
+    g.ntiles = lf.ntiles;
+    g.tbase = w.tile_start[l];
+    g.local = (int32_t)local;
+    g.wlo = w.tile_dep[2 * t];
+    g.whi = w.tile_dep[2 * t + 1];
+    return g;
+}
+
+// Issue the global loads of a tile's inputs into registers (no wait).
+template <typename E, int THREADS, int IPT>
+__device__ __forceinline__ void issue_loads(const E *__restrict__ base_ptr, const TileGeo &g,
+                                            E (&r)[IPT]) {
+    const E *L = base_ptr + g.base;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        int x = threadIdx.x + u * THREADS;
+        if (x < g.n) r[u] = L[x < g.na ? g.a_off + x : g.b_off + x];
+    }
+}
+
 template <typename K, typename V, int THREADS, int IPT>
-__global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
+__global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
                                                        Plan pl, Work w) {
     constexpr int T = THREADS * IPT;
     constexpr bool HAS_V = !std::is_same<V, NoValL>::value;
@@ -41,68 +102,51 @@ __global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *
     extern __shared__ __align__(16) unsigned char smem[];
     K *sk = reinterpret_cast<K *>(smem);
     V *sv = reinterpret_cast<V *>(smem + (size_t)PE * sizeof(K));
-    __shared__ int s_ok;
-
     const int tid = threadIdx.x;
-    const int64_t ntiles = (int64_t)w.ctr->tiles;
-    for (int64_t t = blockIdx.x; t < ntiles && t < pl.cap_tiles; t += gridDim.x) {
-        const int32_t l = w.tile_leaf[t];
-        const Leaf lf = w.leaves[l];
-        const int64_t local = t - w.tile_start[l];
-        const int64_t S = lf.la + lf.lb;
-        const int64_t d0 = local * (int64_t)T;
-        const int64_t d1 = d0 + T < S ? d0 + T : S;
-        const int n = (int)(d1 - d0);
-        const int64_t ia0 = w.tile_rank[t];
-        const int64_t ia1 = (local + 1 < lf.ntiles) ? w.tile_rank[t + 1] : lf.la;
-        // For ascending runs na = ia1 - ia0 already lies in the interval below;
-        // the clamp only keeps every access inside the leaf when a caller
-        // passes unsorted runs (then the result is an unspecified permutation).
-        int64_t na64 = ia1 - ia0;
-        const int64_t na_lo = (d1 - lf.lb - ia0) > 0 ? (d1 - lf.lb - ia0) : 0;
-        const int64_t na_hi = (lf.la - ia0) < (int64_t)n ? (lf.la - ia0) : (int64_t)n;
-        if (na64 < na_lo) na64 = na_lo;
-        if (na64 > na_hi) na64 = na_hi;
-        const int na = (int)na64;
-        const int nb = n - na;
-        const int64_t jb0 = d0 - ia0;
-        K *A = keys + lf.base;
+    int64_t ntiles = (int64_t)w.ctr->tiles;
+    if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
 
-        // 1. load.  Offsets are taken relative to the leaf start (a leaf is
-        // smaller than 2^31 elements), so every address is a uniform base
-        // plus one 32-bit lane offset.
-        {
-            const int a_off = (int)ia0;                       // A-slice start in the leaf
-            const int b_off = (int)(lf.la + jb0) - na;        // B-slice start, minus na
-            K r[IPT];
+    // Software pipeline: the inputs of the next tile of this workgroup are
+    // loaded while the current tile is merged, waits for its readers and is
+    // stored.  The next tile belongs to a later leaf (a leaf has at most
+    // gridDim.x tiles), and no tile of that leaf writes over the next tile's
+    // slices before this workgroup has published the next tile's flag --
+    // after these loads returned.
+    TileGeo g = tile_geo(w, t, T);
+    K r[IPT];
+    V q[HAS_V ? IPT : 1];
+    issue_loads<K, THREADS, IPT>(keys, g, r);
+    if constexpr (HAS_V) issue_loads<V, THREADS, IPT>(vals, g, q);
+
+    for (;;) {
+        // 1. stage the current tile's inputs in LDS
 #pragma unroll
-            for (int u = 0; u < IPT; ++u) {
-                int x = tid + u * THREADS;
-                if (x < n) r[u] = A[x < na ? a_off + x : b_off + x];
-            }
-#pragma unroll
-            for (int u = 0; u < IPT; ++u) {
-                int x = tid + u * THREADS;
-                if (x < n) sk[x] = r[u];
-            }
-            if constexpr (HAS_V) {
-                const V *VL = vals + lf.base;
-                V q[IPT];
-#pragma unroll
-                for (int u = 0; u < IPT; ++u) {
-                    int x = tid + u * THREADS;
-                    if (x < n) q[u] = VL[x < na ? a_off + x : b_off + x];
-                }
-#pragma unroll
-                for (int u = 0; u < IPT; ++u) {
-                    int x = tid + u * THREADS;
-                    if (x < n) sv[x] = q[u];
-                }
+        for (int u = 0; u < IPT; ++u) {
+            int x = tid + u * THREADS;
+            if (x < g.n) {
+                sk[x] = r[u];
+                if constexpr (HAS_V) sv[x] = q[u];
             }
         }
         __syncthreads();
+        if (g.ntiles > 1 && tid == 0)      // this tile's inputs are read
+            __hip_atomic_store(&w.tile_flag[t], pl.epoch, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 
-        // 2. per-thread merge path inside LDS
+        // 2. prefetch the next tile
+        const int64_t tn = t + gridDim.x;
+        const bool has_next = tn < ntiles;
+        TileGeo gn = g;
+        if (has_next) {
+            gn = tile_geo(w, tn, T);
+            issue_loads<K, THREADS, IPT>(keys, gn, r);
+            if constexpr (HAS_V) issue_loads<V, THREADS, IPT>(vals, gn, q);
+        }
+
+        // 3. per-thread merge path inside LDS (stable: ties take A)
+        const int n = g.n, na = g.na, nb = g.n - g.na;
         K out[IPT];
         int src[HAS_V ? IPT : 1];
         {
@@ -116,7 +160,7 @@ __global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *
                 else hi = mid;
             }
             int ia = lo, ib = d - lo;
-            // sk has PE > n entries, so the look-ahead reads below stay inside LDS.
+            // sk has PE > n entries, so the look-ahead reads stay inside LDS.
             K a = sk[ia];
             K b = sk[na + ib];
 #pragma unroll
@@ -134,15 +178,14 @@ __global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *
         if constexpr (HAS_V) {
 #pragma unroll
             for (int e = 0; e < IPT; ++e) {
-                int x = tid * IPT + e;
                 int sidx = src[e];
                 if (sidx > PE - 1) sidx = PE - 1;
-                if (x < n) vout[e] = sv[sidx];
+                vout[e] = sv[sidx];
             }
         }
         __syncthreads();
 
-        // 3. outputs back to LDS, padded: logical x -> x + x/32.  IPT divides
+        // 4. outputs back to LDS, padded: logical x -> x + x/32.  IPT divides
         // 32, so phys(tid*IPT + e) = wbase + e with one base per thread.
         {
             const int wbase = tid * IPT + ((tid * IPT) >> 5);
@@ -157,35 +200,35 @@ __global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *
         }
         __syncthreads();
 
-        // 4. leaf barrier (only leaves with several tiles)
-        // The counter is touched only with relaxed device-scope atomics: the
-        // tile's loads have returned (their values are in LDS), and an
+        // 5. wait until every tile that reads this window has its inputs in
+        // LDS.  Flags are touched only with relaxed device-scope atomics: the
+        // tile's own loads have returned (their values are in LDS), and an
         // acquire/release fence at device scope would write back or
-        // invalidate the whole L2 of this XCD on every poll.
-        if (lf.ntiles > 1) {
-            if (tid == 0) {
-                __hip_atomic_fetch_add(&w.arrive[l], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // invalidate this XCD's whole L2 on every poll.
+        int ok = 1;
+        if (g.ntiles > 1) {
+            int bad = 0;
+            for (int q = g.wlo + tid; q <= g.whi && !bad; q += THREADS) {
+                if (q == g.local) continue;
+                const unsigned *f = &w.tile_flag[g.tbase + q];
                 unsigned spins = 0;
-                int ok = 1;
-                while (__hip_atomic_load(&w.arrive[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                       (unsigned)lf.ntiles) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > kSpinLimit) {
-                        atomicOr(&w.ctr->error, kErrBarrierSpin);
-                        ok = 0;
-                        break;
-                    }
+                while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+                       pl.epoch) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kSpinLimit) { bad = 1; break; }
                 }
-                s_ok = ok;
             }
-            __syncthreads();
-            if (!s_ok) continue;
+            bad = __syncthreads_or(bad);
+            if (bad) {
+                if (tid == 0) atomicOr(&w.ctr->error, kErrBarrierSpin);
+                ok = 0;
+            }
         }
 
-        // 5. coalesced store of the output window; THREADS is a multiple of
+        // 6. coalesced store of the output window; THREADS is a multiple of
         // 32, so phys(tid + u*THREADS) = rbase + u*(THREADS + THREADS/32).
-        {
-            K *O = A + d0;
+        if (ok) {
+            K *O = keys + g.base + g.d0;
             const int rbase = tid + (tid >> 5);
             constexpr int RSTEP = THREADS + THREADS / 32;
 #pragma unroll
@@ -194,7 +237,7 @@ __global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *
                 if (x < n) O[x] = sk[rbase + u * RSTEP];
             }
             if constexpr (HAS_V) {
-                V *OV = vals + lf.base + d0;
+                V *OV = vals + g.base + g.d0;
 #pragma unroll
                 for (int u = 0; u < IPT; ++u) {
                     int x = tid + u * THREADS;
@@ -203,6 +246,9 @@ __global__ __launch_bounds__(THREADS) void k_leafmerge(K *__restrict__ keys, V *
             }
         }
         __syncthreads();
+        if (!has_next) break;
+        t = tn;
+        g = gn;
     }
 }
 
@@ -227,7 +273,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Plan pl, Work w) {
             my_elems += (unsigned long long)S;
             c = (S + pl.tile - 1) / pl.tile;
             w.leaves[l].ntiles = (int32_t)c;
-            w.arrive[l] = 0u;
         }
         buf[tid] = c;
         __syncthreads();
@@ -257,6 +302,81 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Plan pl, Work w) {
     }
 }
 
+// Readers of each tile's window.  Tile i of a leaf (parts la, lb, size S)
+// writes [iT, min((i+1)T, S)).  The A elements there, [iT, min((i+1)T, la)),
+// are read by the tiles j whose A-slice [ia(j), ia(j+1)) meets that range;
+// A elements only move right, so these are tiles >= i and the last one is
+// the last j with ia(j) < min((i+1)T, la).  The B elements there, B indices
+// [max(iT, la) - la, min((i+1)T, S) - la), only move left: their readers
+// are tiles <= i, the first being the first j with jb(j+1) > max(iT,la)-la,
+// where jb(j) = min(jT, S) - ia(j).  dep = [first B reader, last A reader].
+__global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
+    int64_t ntiles = (int64_t)w.ctr->tiles;
+    if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
+    const int64_t T = pl.tile;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t l = w.tile_leaf[t];
+        const Leaf lf = w.leaves[l];
+        const int64_t ts = w.tile_start[l];
+        const int64_t nt = lf.ntiles;
+        const int64_t i = t - ts;
+        const int64_t S = lf.la + lf.lb;
+        int64_t wlo = i, whi = i;
+        if (nt > 1) {
+            auto ia = [&](int64_t j) -> int64_t { return j < nt ? w.tile_rank[ts + j] : lf.la; };
+            auto jb = [&](int64_t j) -> int64_t {
+                int64_t d = j * T < S ? j * T : S;
+                return d - ia(j);
+            };
+            const int64_t pa0 = i * T;
+            const int64_t pa1 = (i + 1) * T < lf.la ? (i + 1) * T : lf.la;
+            if (pa0 < lf.la) {                       // window holds A elements
+                int64_t lo = 0, hi = nt - 1;         // ia(0) = 0 < pa1
+                while (lo < hi) {
+                    int64_t mid = (lo + hi + 1) >> 1;
+                    if (ia(mid) < pa1) lo = mid; else hi = mid - 1;
+                }
+                if (lo > whi) whi = lo;
+            }
+            const int64_t e = (i + 1) * T < S ? (i + 1) * T : S;
+            if (e > lf.la) {                         // window holds B elements
+                const int64_t pb0 = (pa0 > lf.la ? pa0 : lf.la) - lf.la;
+                int64_t lo = 0, hi = nt - 1;         // jb(nt) = lb > pb0
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    if (jb(mid + 1) > pb0) hi = mid; else lo = mid + 1;
+                }
+                if (lo < wlo) wlo = lo;
+            }
+        }
+        w.tile_dep[2 * t] = (int32_t)wlo;
+        w.tile_dep[2 * t + 1] = (int32_t)whi;
+    }
+}
+
+__global__ void k_fill32(unsigned *p, int64_t n, unsigned v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_tiledeps(const Plan &pl, const Work &w, hipStream_t s) {
+    int64_t g = (pl.cap_tiles + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_tiledeps, dim3((int)g), dim3(256), 0, s, pl, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill32, dim3((int)g), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_plan(const Plan &pl, const Work &w, hipStream_t s) {
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, pl, w);
     return hipGetLastError();
@@ -276,7 +396,7 @@ struct LeafCfg {
 // (key bytes, payload bytes) -> (threads, items per thread)
 static void geom(int ek, int ev, int *th, int *ipt) {
     if (ev == 0) { *th = 512; *ipt = ek == 4 ? 16 : 8; return; }
-    if (ek == 4 && ev == 4) { *th = 512; *ipt = 16; return; }
+    if (ek == 4 && ev == 4) { *th = 512; *ipt = 8; return; }
     *th = 512; *ipt = 8;
 }
 
@@ -292,8 +412,8 @@ void leaf_geometry(int esize_k, int esize_v, int *threads, int *ipt, size_t *lds
     X(uint32_t, NoValL, 512, 16)                \
     X(int64_t, NoValL, 512, 8)                  \
     X(uint64_t, NoValL, 512, 8)                 \
-    X(int32_t, uint32_t, 512, 16)               \
-    X(uint32_t, uint32_t, 512, 16)              \
+    X(int32_t, uint32_t, 512, 8)                \
+    X(uint32_t, uint32_t, 512, 8)               \
     X(int64_t, uint32_t, 512, 8)                \
     X(uint64_t, uint32_t, 512, 8)               \
     X(int32_t, uint64_t, 512, 8)                \
