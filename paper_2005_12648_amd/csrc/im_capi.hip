@@ -134,18 +134,23 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->total = total;
     pl->tile = (int64_t)th * ipt;
     pl->leaf_cap = tiles_per_leaf * pl->tile;
+    // A leaf may be larger than the grid when its smaller part keeps every
+    // element within G-2 tiles of its source (im_leaf.hip, slot order).
+    pl->leaf_span = (tiles_per_leaf > 2 ? tiles_per_leaf - 2 : 0) * pl->tile;
     pl->grid_leaf = G;
     if (max_inst <= 0 || max_inst > total) max_inst = total;
     // Division levels: children are at most 9/16 of the parent (plus one for
-    // rounding), the last level only classifies.
+    // rounding); a node of at most max(leaf_cap, 2*leaf_span) elements is a
+    // leaf; the last level only classifies.
+    const double stop = (double)std::max<int64_t>(pl->leaf_cap, 2 * pl->leaf_span);
     int lv = 1;
     double sz = (double)max_inst;
-    while (sz > (double)pl->leaf_cap && lv < kMaxLevels) {
+    while (sz > stop && lv < kMaxLevels) {
         sz = sz * 9.0 / 16.0 + 1.0;
         ++lv;
     }
     pl->max_levels = lv;
-    int64_t per = total / pl->leaf_cap + 1;
+    int64_t per = total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
     pl->cap_nodes = std::max<int64_t>(n_inst, 2 * per) + 16;
     pl->cap_rot = pl->cap_nodes;
     pl->cap_leaves = n_inst + 2 * (int64_t)lv * per + 16;

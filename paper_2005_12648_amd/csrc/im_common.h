@@ -45,10 +45,14 @@ struct Rot {
     int64_t nw;   // work items
 };
 
-// A pair that is merged without further division.
+// A pair that is merged without further division.  Its tiles are processed
+// in increasing order (dir 0: every A element moves right by at most
+// leaf_span elements) or in decreasing order (dir 1: every B element moves
+// left by at most leaf_span elements).
 struct Leaf {
     int64_t base, la, lb, k0, i0;
     int32_t inst, ntiles;
+    int32_t dir, pad;
 };
 
 // Device counters.  Zeroed by k_init at the start of every call.
@@ -88,7 +92,8 @@ struct MlpDev {
 struct Plan {
     int64_t n_inst;
     int64_t total;          // bound of the elements in all instances
-    int64_t leaf_cap;       // largest pair merged without division (elements)
+    int64_t leaf_cap;       // a pair of at most this many elements is a leaf
+    int64_t leaf_span;      // ... and so is a pair whose smaller part has at most this many
     int64_t tile;           // elements per workgroup tile in the leaf merge
     int32_t max_levels;     // division levels enqueued
     int32_t grid_leaf;      // persistent grid of the leaf merge

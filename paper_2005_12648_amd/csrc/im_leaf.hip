@@ -17,13 +17,17 @@
 //      B elements only move left, so the readers form one contiguous range
 //      of tiles around the tile itself);
 //   5. coalesced store of the window.
-// The grid is persistent and co-resident (cooperative launch); tile t is
-// handled by workgroup t mod G in increasing t, and a leaf has at most G
-// tiles, so every tile a waiting tile depends on is either done or held by a
-// workgroup that has finished all its earlier tiles -- the smallest
-// unfinished tile always makes progress and the waits cannot deadlock.  The
-// wait is bounded: on expiry the workgroup raises an error bit and skips its
-// store.
+// The grid is persistent and co-resident (cooperative launch); processing
+// slot s is handled by workgroup s mod G in increasing s.  Within a leaf the
+// slots visit the tiles in increasing order when every A element moves right
+// by at most (G-2) tiles (the leaf's B-part is within the leaf span, or the
+// whole leaf has at most G tiles), else in decreasing order (then its A-part
+// is within the span and every B element moves left by at most (G-2) tiles).
+// Either way every tile that reads a window lies less than G slots after
+// it, so the workgroup holding it has finished all its earlier slots: the
+// smallest unfinished slot always makes progress and the waits cannot
+// deadlock.  The wait is bounded: on expiry the workgroup raises an error
+// bit and skips its store.
 #include <type_traits>
 #include "im_common.h"
 
@@ -44,11 +48,15 @@ struct TileGeo {
     int32_t leaf, ntiles, local, wlo, whi;
 };
 
-__device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t t, int T) {
+// Geometry of the tile processed in slot s (the slot order reverses the
+// tiles of a dir-1 leaf).
+__device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t s, int T) {
     TileGeo g;
-    const int32_t l = w.tile_leaf[t];
+    const int32_t l = w.tile_leaf[s];
     const Leaf lf = w.leaves[l];
-    const int64_t local = t - w.tile_start[l];
+    const int64_t sl = s - w.tile_start[l];
+    const int64_t local = lf.dir ? (int64_t)lf.ntiles - 1 - sl : sl;
+    const int64_t t = w.tile_start[l] + local;
     const int64_t S = lf.la + lf.lb;
     const int64_t d0 = local * (int64_t)T;
     const int64_t d1 = d0 + T < S ? d0 + T : S;
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
         }
         __syncthreads();
         if (g.ntiles > 1 && tid == 0)      // this tile's inputs are read
-            __hip_atomic_store(&w.tile_flag[t], pl.epoch, __ATOMIC_RELAXED,
+            __hip_atomic_store(&w.tile_flag[g.tbase + g.local], pl.epoch, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
 
         // 2. prefetch the next tile

@@ -13,7 +13,8 @@
 //     before the search) and of the entry of Alg. 2/3: an empty part, or
 //     A[last] <= B[0], leaves the node as it is; A[0] > B[last] needs a single
 //     exchange B|A and no merge;
-//   * S <= leaf capacity: the node is a leaf (merged in LDS, im_leaf.hip);
+//   * S <= leaf capacity, or the smaller part within the leaf span: the node
+//     is a leaf (merged tile by tile in LDS, im_leaf.hip);
 //   * otherwise the split diagonal is k = la when max(la, lb) <= 9/16 S --
 //     then the two exchanged partitions have the same length (la - i == j),
 //     so the exchange is a single block swap -- else k = S/2 (balanced
@@ -95,6 +96,10 @@ __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const N
     Leaf lf;
     lf.base = nd.base; lf.la = nd.la; lf.lb = nd.lb; lf.k0 = nd.k0; lf.i0 = nd.i0;
     lf.inst = nd.inst; lf.ntiles = 0;
+    // direction of the tile order: the part that bounds how far elements
+    // travel must be the one within leaf_span (see im_leaf.hip)
+    lf.dir = (nd.la + nd.lb <= pl.leaf_cap || nd.lb <= pl.leaf_span) ? 0 : 1;
+    lf.pad = 0;
     w.leaves[slot] = lf;
 }
 
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
             continue;
         }
         const int64_t S = la + lb;
-        if (S <= pl.leaf_cap) {
+        if (S <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) {
             emit_leaf(pl, w, nd);
             continue;
         }
