@@ -59,6 +59,7 @@ struct Leaf {
 struct Counters {
     unsigned long long level_nodes[kMaxLevels + 1];  // nodes at each level
     unsigned long long level_rot[kMaxLevels];        // (count << 40) | work items
+    unsigned long long level_rev[kMaxLevels];        // exchanges needing phase B
     unsigned long long leaves;
     unsigned long long tiles;
     unsigned long long rotated;       // elements moved by exchanges

@@ -95,6 +95,7 @@ __global__ __launch_bounds__(kRotThreads) void k_rotate(EK *__restrict__ keys, E
                                                         const Rot *__restrict__ rot,
                                                         const Counters *__restrict__ ctr,
                                                         int64_t cap_rot, int level, int phase) {
+    if (phase == 1 && ctr->level_rev[level] == 0) return;   // only block swaps
     const unsigned long long packed = ctr->level_rot[level];
     int64_t nrot = (int64_t)(packed >> kRotCountShift);
     if (nrot > cap_rot) nrot = cap_rot;

@@ -84,7 +84,10 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
     r.nw = nw;
     w.rot[slot] = r;
     atomicAdd(&w.ctr->rotated, (unsigned long long)(lx + ly));
-    if (lx != ly) atomicAdd(&w.ctr->rotated_rev, (unsigned long long)(lx + ly));
+    if (lx != ly) {
+        atomicAdd(&w.ctr->rotated_rev, (unsigned long long)(lx + ly));
+        atomicAdd(&w.ctr->level_rev[level], 1ull);
+    }
 }
 
 __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const Node &nd) {
@@ -103,6 +106,8 @@ __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const N
     w.leaves[slot] = lf;
 }
 
+// One wavefront per node: the split search is the wave-cooperative 64-ary
+// co-rank (a handful of dependent rounds), lane 0 emits the results.
 template <typename K, bool LEARNED>
 __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ data,
                                                          const int64_t *__restrict__ offsets,
@@ -111,28 +116,30 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
     const unsigned long long cnt = w.ctr->level_nodes[level];
     const Node *in = w.nodes[level & 1];
     Node *out = w.nodes[(level + 1) & 1];
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (gid == 0 && cnt > 0) atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
-    uint32_t probes = 0, searches = 0;
-    for (int64_t idx = gid; idx < (int64_t)cnt && idx < pl.cap_nodes; idx += stride) {
-        Node nd = in[idx];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    if (wave == 0 && lane == 0 && cnt > 0)
+        atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
+    uint32_t rounds = 0, searches = 0;
+    for (int64_t idx = wave; idx < (int64_t)cnt && idx < pl.cap_nodes; idx += nwaves) {
+        const Node nd = in[idx];
         const int64_t la = nd.la, lb = nd.lb;
         if (la == 0 || lb == 0) continue;                       // nothing to merge
         const K *A = data + nd.base;
         const K *B = A + la;
         if (A[la - 1] <= B[0]) continue;                        // already in order
         if (A[0] > B[lb - 1]) {                                 // every B before every A
-            emit_rot(pl, w, level, nd.base, la, lb);
+            if (lane == 0) emit_rot(pl, w, level, nd.base, la, lb);
             continue;
         }
         const int64_t S = la + lb;
         if (S <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) {
-            emit_leaf(pl, w, nd);
+            if (lane == 0) emit_leaf(pl, w, nd);
             continue;
         }
         if (level + 1 >= pl.max_levels) {                       // depth bound violated
-            atomicOr(&w.ctr->error, kErrOversizeLeaf);
+            if (lane == 0) atomicOr(&w.ctr->error, kErrOversizeLeaf);
             continue;
         }
         const int64_t mx = la > lb ? la : lb;
@@ -142,10 +149,12 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
         if (LEARNED) {
             int64_t o0 = offsets[2 * nd.inst], o1 = offsets[2 * nd.inst + 1],
                     o2 = offsets[2 * nd.inst + 2];
-            i = corank_learned(A, la, B, lb, k, mlp, nd.k0 + k, o2 - o0, o1 - o0, nd.i0, probes);
+            i = corank_wave_learned(A, la, B, lb, k, mlp, nd.k0 + k, o2 - o0, o1 - o0, nd.i0,
+                                    rounds);
         } else {
-            i = corank_plain(A, la, B, lb, k, probes);
+            i = corank_wave(A, la, B, lb, k, rounds);
         }
+        if (lane != 0) continue;
         const int64_t j = k - i;
         // Alg. 3 "shift": exchange A[i, la) and B[0, j) -> ... A_0 B_0 A_1 B_1
         if (la - i > 0 && j > 0) emit_rot(pl, w, level, nd.base + i, la - i, j);
@@ -161,9 +170,9 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
         out[slot] = l;
         out[slot + 1] = r;
     }
-    if (searches) {
+    if (lane == 0 && searches) {
         atomicAdd(&w.ctr->searches, (unsigned long long)searches);
-        atomicAdd(&w.ctr->probes, (unsigned long long)probes);
+        atomicAdd(&w.ctr->probes, (unsigned long long)rounds);
     }
 }
 
@@ -276,7 +285,7 @@ hipError_t launch_init(const Plan &pl, const Work &w, const int64_t *d_offsets, 
 template <typename K>
 static hipError_t split_t(const void *data, const int64_t *offs, const Plan &pl, const Work &w,
                           int level, const MlpDev *mlp, hipStream_t s) {
-    int g = grid_for(pl.cap_nodes, kSplitThreads, 2048);
+    int g = grid_for(pl.cap_nodes * 64, kSplitThreads, 4096);   // one wave per node
     if (mlp)
         hipLaunchKernelGGL((k_split<K, true>), dim3(g), dim3(kSplitThreads), 0, s,
                            (const K *)data, offs, pl, w, level, mlp);
