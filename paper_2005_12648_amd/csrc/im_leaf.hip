@@ -38,7 +38,7 @@ struct NoValL {};
 constexpr unsigned kSpinLimit = 1u << 26;
 
 template <int T>
-struct LdsPad { static constexpr int elems = T + T / 32 + 1; };
+struct LdsPad { static constexpr int elems = T + 2; };   // + look-ahead slack
 
 // Geometry of one tile: its leaf, output window [d0, d0+n) inside the leaf,
 // and where its A-slice (na elements) and B-slice (n - na) start.
@@ -88,75 +88,76 @@ __device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t s, int T) {
     return g;
 }
 
-// Issue the global loads of a tile's inputs into registers (no wait).
+// Copy a tile's A-slice and B-slice (one contiguous logical range [0, n))
+// into LDS with LDS-DMA loads (global_load_lds_dword): no registers, every
+// load of the tile in flight at once.  The copy runs over 32-bit words: lane
+// slot j = tid + u*THREADS moves word j of the LDS image, i.e. word j % D of
+// element j / D (D words per element); a wave's 64 slots are contiguous in
+// LDS, as the DMA requires (destination = wave base + 4 * lane).  The caller
+// waits for completion (vmcnt) before reading.
 template <typename E, int THREADS, int IPT>
-__device__ __forceinline__ void issue_loads(const E *__restrict__ base_ptr, const TileGeo &g,
-                                            E (&r)[IPT]) {
-    const E *L = base_ptr + g.base;
+__device__ __forceinline__ void stage_tile_dma(const E *__restrict__ base_ptr, const TileGeo &g,
+                                               E *__restrict__ s) {
+    constexpr int D = (int)(sizeof(E) / 4);
+    const uint32_t *L = reinterpret_cast<const uint32_t *>(base_ptr + g.base);
+    uint32_t *S = reinterpret_cast<uint32_t *>(s);
+    int xb = threadIdx.x;
+    asm volatile("" : "+v"(xb));
+    const int wbase = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
+    const int nw = g.n * D;
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-        int x = threadIdx.x + u * THREADS;
-        if (x < g.n) r[u] = L[x < g.na ? g.a_off + x : g.b_off + x];
+    for (int u = 0; u < IPT * D; ++u) {
+        const int j = xb + u * THREADS;
+        if (j < nw) {
+            const int x = j / D;                      // D is 1 or 2: a shift
+            const int src = x < g.na ? g.a_off + x : g.b_off + x;
+            __builtin_amdgcn_global_load_lds(L + (int64_t)src * D + (j - x * D),
+                                             S + wbase + u * THREADS, 4, 0, 0);
+        }
     }
 }
 
+__device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Pipeline per workgroup (slots t, t+G, t+2G, ...):
+//   merge(t) from LDS into registers -> transpose the outputs through LDS
+//   (blocked -> striped) -> stage(t+G) into LDS and publish its flag ->
+//   wait for the readers of t's window -> coalesced store of t from
+//   registers.
+// The next tile is staged and flagged before this tile waits, so a tile's
+// flag only needs the workgroup's slot two rounds back to be finished: the
+// readers (at most G-1 slots ahead, see the leaf span) are always reachable
+// with a full round of slack, and waits rarely stall.
 template <typename K, typename V, int THREADS, int IPT>
 __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
-                                                       Plan pl, Work w) {
+                                                          Plan pl, Work w) {
     constexpr int T = THREADS * IPT;
     constexpr bool HAS_V = !std::is_same<V, NoValL>::value;
     constexpr int PE = LdsPad<T>::elems;
-    static_assert(32 % IPT == 0 && THREADS % 32 == 0, "padding layout");
     extern __shared__ __align__(16) unsigned char smem[];
     K *sk = reinterpret_cast<K *>(smem);
     V *sv = reinterpret_cast<V *>(smem + (size_t)PE * sizeof(K));
+
     const int tid = threadIdx.x;
     int64_t ntiles = (int64_t)w.ctr->tiles;
     if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
 
-    // Software pipeline: the inputs of the next tile of this workgroup are
-    // loaded while the current tile is merged, waits for its readers and is
-    // stored.  The next tile belongs to a later leaf (a leaf has at most
-    // gridDim.x tiles), and no tile of that leaf writes over the next tile's
-    // slices before this workgroup has published the next tile's flag --
-    // after these loads returned.
     TileGeo g = tile_geo(w, t, T);
-    K r[IPT];
-    V q[HAS_V ? IPT : 1];
-    issue_loads<K, THREADS, IPT>(keys, g, r);
-    if constexpr (HAS_V) issue_loads<V, THREADS, IPT>(vals, g, q);
+    stage_tile_dma<K, THREADS, IPT>(keys, g, sk);
+    if constexpr (HAS_V) stage_tile_dma<V, THREADS, IPT>(vals, g, sv);
+    wait_dma();
+    __syncthreads();
+    if (g.ntiles > 1 && tid == 0)            // this tile's inputs are read
+        __hip_atomic_store(&w.tile_flag[g.tbase + g.local], pl.epoch, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 
     for (;;) {
-        // 1. stage the current tile's inputs in LDS
-#pragma unroll
-        for (int u = 0; u < IPT; ++u) {
-            int x = tid + u * THREADS;
-            if (x < g.n) {
-                sk[x] = r[u];
-                if constexpr (HAS_V) sv[x] = q[u];
-            }
-        }
-        __syncthreads();
-        if (g.ntiles > 1 && tid == 0)      // this tile's inputs are read
-            __hip_atomic_store(&w.tile_flag[g.tbase + g.local], pl.epoch, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-
-        // 2. prefetch the next tile
-        const int64_t tn = t + gridDim.x;
-        const bool has_next = tn < ntiles;
-        TileGeo gn = g;
-        if (has_next) {
-            gn = tile_geo(w, tn, T);
-            issue_loads<K, THREADS, IPT>(keys, gn, r);
-            if constexpr (HAS_V) issue_loads<V, THREADS, IPT>(vals, gn, q);
-        }
-
-        // 3. per-thread merge path inside LDS (stable: ties take A)
+        // 1. per-thread merge path inside LDS (stable: ties take A)
         const int n = g.n, na = g.na, nb = g.n - g.na;
         K out[IPT];
-        int src[HAS_V ? IPT : 1];
+        V vout[HAS_V ? IPT : 1];
         {
             int d = tid * IPT;
             if (d > n) d = n;
@@ -175,42 +176,61 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
             for (int e = 0; e < IPT; ++e) {
                 bool ta = (ib >= nb) || (ia < na && a <= b);
                 out[e] = ta ? a : b;
-                if constexpr (HAS_V) src[e] = ta ? ia : na + ib;
-                int nx = ta ? ia + 1 : na + ib + 1;
+                int src = ta ? ia : na + ib;
+                if constexpr (HAS_V) vout[e] = sv[src > PE - 1 ? PE - 1 : src];
+                int nx = src + 1;
                 if (nx > PE - 1) nx = PE - 1;
                 K v = sk[nx];
                 if (ta) { ++ia; a = v; } else { ++ib; b = v; }
             }
         }
-        V vout[HAS_V ? IPT : 1];
-        if constexpr (HAS_V) {
-#pragma unroll
-            for (int e = 0; e < IPT; ++e) {
-                int sidx = src[e];
-                if (sidx > PE - 1) sidx = PE - 1;
-                vout[e] = sv[sidx];
-            }
-        }
-        __syncthreads();
+        __syncthreads();                     // LDS inputs of this tile are dead
 
-        // 4. outputs back to LDS, padded: logical x -> x + x/32.  IPT divides
-        // 32, so phys(tid*IPT + e) = wbase + e with one base per thread.
+        // 2. blocked -> striped through LDS: thread p holds outputs
+        // p*IPT + e; after the round trip it holds tid + u*THREADS, so the
+        // final stores are coalesced.  IPT is odd: the blocked writes (stride
+        // IPT words) hit distinct banks.
         {
-            const int wbase = tid * IPT + ((tid * IPT) >> 5);
             const int x0 = tid * IPT;
 #pragma unroll
             for (int e = 0; e < IPT; ++e) {
                 if (x0 + e < n) {
-                    sk[wbase + e] = out[e];
-                    if constexpr (HAS_V) sv[wbase + e] = vout[e];
+                    sk[x0 + e] = out[e];
+                    if constexpr (HAS_V) sv[x0 + e] = vout[e];
                 }
             }
+            __syncthreads();
+            int xb = tid;
+            asm volatile("" : "+v"(xb));
+#pragma unroll
+            for (int u = 0; u < IPT; ++u) {
+                const int x = xb + u * THREADS;
+                if (x < n) {
+                    out[u] = sk[x];
+                    if constexpr (HAS_V) vout[u] = sv[x];
+                }
+            }
+            __syncthreads();
+        }
+
+        // 3. stage the next tile of this workgroup and publish its flag
+        const int64_t tn = t + gridDim.x;
+        const bool has_next = tn < ntiles;
+        TileGeo gn = g;
+        if (has_next) {
+            gn = tile_geo(w, tn, T);
+            stage_tile_dma<K, THREADS, IPT>(keys, gn, sk);
+            if constexpr (HAS_V) stage_tile_dma<V, THREADS, IPT>(vals, gn, sv);
+            wait_dma();
         }
         __syncthreads();
+        if (has_next && gn.ntiles > 1 && tid == 0)
+            __hip_atomic_store(&w.tile_flag[gn.tbase + gn.local], pl.epoch, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 
-        // 5. wait until every tile that reads this window has its inputs in
+        // 4. wait until every tile that reads this window has its inputs in
         // LDS.  Flags are touched only with relaxed device-scope atomics: the
-        // tile's own loads have returned (their values are in LDS), and an
+        // readers' loads have returned before they publish, and an
         // acquire/release fence at device scope would write back or
         // invalidate this XCD's whole L2 on every poll.
         int ok = 1;
@@ -233,27 +253,25 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
             }
         }
 
-        // 6. coalesced store of the output window; THREADS is a multiple of
-        // 32, so phys(tid + u*THREADS) = rbase + u*(THREADS + THREADS/32).
+        // 5. coalesced store of this tile's window from registers
         if (ok) {
+            int xb = tid;
+            asm volatile("" : "+v"(xb));
             K *O = keys + g.base + g.d0;
-            const int rbase = tid + (tid >> 5);
-            constexpr int RSTEP = THREADS + THREADS / 32;
 #pragma unroll
             for (int u = 0; u < IPT; ++u) {
-                int x = tid + u * THREADS;
-                if (x < n) O[x] = sk[rbase + u * RSTEP];
+                const int x = xb + u * THREADS;
+                if (x < n) O[x] = out[u];
             }
             if constexpr (HAS_V) {
                 V *OV = vals + g.base + g.d0;
 #pragma unroll
                 for (int u = 0; u < IPT; ++u) {
-                    int x = tid + u * THREADS;
-                    if (x < n) OV[x] = sv[rbase + u * RSTEP];
+                    const int x = xb + u * THREADS;
+                    if (x < n) OV[x] = vout[u];
                 }
             }
         }
-        __syncthreads();
         if (!has_next) break;
         t = tn;
         g = gn;
@@ -401,33 +419,36 @@ struct LeafCfg {
     static const void *fn() { return (const void *)&k_leafmerge<K, V, THREADS, IPT>; }
 };
 
-// (key bytes, payload bytes) -> (threads, items per thread)
+// (key bytes, payload bytes) -> (threads, items per thread).  Items per
+// thread are odd and sized so that a tile takes about 70 KB of LDS: two
+// workgroups fill a CU's LDS, and the tiles resident on the whole chip --
+// which bound how far a leaf may move its elements -- hold about 40 MB.
 static void geom(int ek, int ev, int *th, int *ipt) {
-    if (ev == 0) { *th = 512; *ipt = ek == 4 ? 16 : 8; return; }
-    if (ek == 4 && ev == 4) { *th = 512; *ipt = 8; return; }
-    *th = 512; *ipt = 8;
+    *th = 512;
+    const int eb = ek + ev;
+    *ipt = eb <= 4 ? 35 : (eb <= 8 ? 17 : (eb <= 12 ? 11 : 9));
 }
 
 void leaf_geometry(int esize_k, int esize_v, int *threads, int *ipt, size_t *lds_bytes) {
     geom(esize_k, esize_v, threads, ipt);
     int T = *threads * *ipt;
-    size_t pe = (size_t)(T + T / 32 + 1);
+    size_t pe = (size_t)(T + 2);
     *lds_bytes = pe * esize_k + pe * esize_v;
 }
 
 #define IM_LEAF_CASES(X)                        \
-    X(int32_t, NoValL, 512, 16)                 \
-    X(uint32_t, NoValL, 512, 16)                \
-    X(int64_t, NoValL, 512, 8)                  \
-    X(uint64_t, NoValL, 512, 8)                 \
-    X(int32_t, uint32_t, 512, 8)                \
-    X(uint32_t, uint32_t, 512, 8)               \
-    X(int64_t, uint32_t, 512, 8)                \
-    X(uint64_t, uint32_t, 512, 8)               \
-    X(int32_t, uint64_t, 512, 8)                \
-    X(uint32_t, uint64_t, 512, 8)               \
-    X(int64_t, uint64_t, 512, 8)                \
-    X(uint64_t, uint64_t, 512, 8)
+    X(int32_t, NoValL, 512, 35)                 \
+    X(uint32_t, NoValL, 512, 35)                \
+    X(int64_t, NoValL, 512, 17)                 \
+    X(uint64_t, NoValL, 512, 17)                \
+    X(int32_t, uint32_t, 512, 17)               \
+    X(uint32_t, uint32_t, 512, 17)              \
+    X(int64_t, uint32_t, 512, 11)               \
+    X(uint64_t, uint32_t, 512, 11)              \
+    X(int32_t, uint64_t, 512, 11)               \
+    X(uint32_t, uint64_t, 512, 11)              \
+    X(int64_t, uint64_t, 512, 9)                \
+    X(uint64_t, uint64_t, 512, 9)
 
 template <typename K> struct KeyOf;
 template <> struct KeyOf<int32_t> { static constexpr int code = kI32; };

@@ -106,69 +106,90 @@ __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const N
     w.leaves[slot] = lf;
 }
 
-// One wavefront per node: the split search is the wave-cooperative 64-ary
-// co-rank (a handful of dependent rounds), lane 0 emits the results.
+// One lane per node classifies it (early exits, leaf); the nodes of a wave
+// that must be split are then searched one after another by the whole wave
+// with the cooperative 64-ary co-rank (a handful of dependent rounds).
 template <typename K, bool LEARNED>
 __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ data,
                                                          const int64_t *__restrict__ offsets,
                                                          Plan pl, Work w, int level,
                                                          const MlpDev *__restrict__ mlp) {
-    const unsigned long long cnt = w.ctr->level_nodes[level];
+    const unsigned long long cnt_raw = w.ctr->level_nodes[level];
+    const int64_t cnt = (int64_t)cnt_raw < pl.cap_nodes ? (int64_t)cnt_raw : pl.cap_nodes;
     const Node *in = w.nodes[level & 1];
     Node *out = w.nodes[(level + 1) & 1];
     const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    if (wave == 0 && lane == 0 && cnt > 0)
-        atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (gid == 0 && cnt > 0) atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
     uint32_t rounds = 0, searches = 0;
-    for (int64_t idx = wave; idx < (int64_t)cnt && idx < pl.cap_nodes; idx += nwaves) {
-        const Node nd = in[idx];
-        const int64_t la = nd.la, lb = nd.lb;
-        if (la == 0 || lb == 0) continue;                       // nothing to merge
-        const K *A = data + nd.base;
-        const K *B = A + la;
-        if (A[la - 1] <= B[0]) continue;                        // already in order
-        if (A[0] > B[lb - 1]) {                                 // every B before every A
-            if (lane == 0) emit_rot(pl, w, level, nd.base, la, lb);
-            continue;
+    for (int64_t idx0 = gid - lane; idx0 < cnt; idx0 += stride) {   // wave-uniform
+        const int64_t idx = idx0 + lane;
+        Node nd;
+        bool split = false;
+        int64_t k = 0;
+        if (idx < cnt) {
+            nd = in[idx];
+            const int64_t la = nd.la, lb = nd.lb;
+            const K *A = data + nd.base;
+            const K *B = A + la;
+            if (la == 0 || lb == 0) {
+                // nothing to merge
+            } else if (A[la - 1] <= B[0]) {
+                // already in order
+            } else if (A[0] > B[lb - 1]) {
+                emit_rot(pl, w, level, nd.base, la, lb);     // every B before every A
+            } else if (la + lb <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) {
+                emit_leaf(pl, w, nd);
+            } else if (level + 1 >= pl.max_levels) {
+                atomicOr(&w.ctr->error, kErrOversizeLeaf);   // depth bound violated
+            } else {
+                const int64_t S = la + lb;
+                const int64_t mx = la > lb ? la : lb;
+                k = (mx * 16 <= S * 9) ? la : S / 2;
+                split = true;
+            }
         }
-        const int64_t S = la + lb;
-        if (S <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) {
-            if (lane == 0) emit_leaf(pl, w, nd);
-            continue;
+        unsigned long long todo = __ballot(split);
+        while (todo) {
+            const int src = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t base = __shfl(nd.base, src, 64);
+            const int64_t la = __shfl(nd.la, src, 64);
+            const int64_t lb = __shfl(nd.lb, src, 64);
+            const int64_t kk = __shfl(k, src, 64);
+            const K *A = data + base;
+            const K *B = A + la;
+            int64_t i;
+            ++searches;
+            if (LEARNED) {
+                const int64_t k0 = __shfl(nd.k0, src, 64);
+                const int64_t i0 = __shfl(nd.i0, src, 64);
+                const int inst = __shfl(nd.inst, src, 64);
+                int64_t o0 = offsets[2 * inst], o1 = offsets[2 * inst + 1],
+                        o2 = offsets[2 * inst + 2];
+                i = corank_wave_learned(A, la, B, lb, kk, mlp, k0 + kk, o2 - o0, o1 - o0, i0,
+                                        rounds);
+            } else {
+                i = corank_wave(A, la, B, lb, kk, rounds);
+            }
+            if (lane != src) continue;
+            const int64_t j = kk - i;
+            // Alg. 3 "shift": exchange A[i, la) and B[0, j) -> ... A_0 B_0 A_1 B_1
+            if (la - i > 0 && j > 0) emit_rot(pl, w, level, base + i, la - i, j);
+            unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level + 1], 2ull);
+            if ((int64_t)slot + 1 >= pl.cap_nodes) {
+                atomicOr(&w.ctr->error, kErrCapacity);
+                continue;
+            }
+            Node l, r;
+            l.base = base; l.la = i; l.lb = j; l.k0 = nd.k0; l.i0 = nd.i0; l.inst = nd.inst;
+            l.pad = 0;
+            r.base = base + kk; r.la = la - i; r.lb = lb - j; r.k0 = nd.k0 + kk;
+            r.i0 = nd.i0 + i; r.inst = nd.inst; r.pad = 0;
+            out[slot] = l;
+            out[slot + 1] = r;
         }
-        if (level + 1 >= pl.max_levels) {                       // depth bound violated
-            if (lane == 0) atomicOr(&w.ctr->error, kErrOversizeLeaf);
-            continue;
-        }
-        const int64_t mx = la > lb ? la : lb;
-        const int64_t k = (mx * 16 <= S * 9) ? la : S / 2;
-        int64_t i;
-        ++searches;
-        if (LEARNED) {
-            int64_t o0 = offsets[2 * nd.inst], o1 = offsets[2 * nd.inst + 1],
-                    o2 = offsets[2 * nd.inst + 2];
-            i = corank_wave_learned(A, la, B, lb, k, mlp, nd.k0 + k, o2 - o0, o1 - o0, nd.i0,
-                                    rounds);
-        } else {
-            i = corank_wave(A, la, B, lb, k, rounds);
-        }
-        if (lane != 0) continue;
-        const int64_t j = k - i;
-        // Alg. 3 "shift": exchange A[i, la) and B[0, j) -> ... A_0 B_0 A_1 B_1
-        if (la - i > 0 && j > 0) emit_rot(pl, w, level, nd.base + i, la - i, j);
-        unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level + 1], 2ull);
-        if ((int64_t)slot + 1 >= pl.cap_nodes) {
-            atomicOr(&w.ctr->error, kErrCapacity);
-            continue;
-        }
-        Node l, r;
-        l.base = nd.base; l.la = i; l.lb = j; l.k0 = nd.k0; l.i0 = nd.i0; l.inst = nd.inst; l.pad = 0;
-        r.base = nd.base + k; r.la = la - i; r.lb = lb - j; r.k0 = nd.k0 + k; r.i0 = nd.i0 + i;
-        r.inst = nd.inst; r.pad = 0;
-        out[slot] = l;
-        out[slot + 1] = r;
     }
     if (lane == 0 && searches) {
         atomicAdd(&w.ctr->searches, (unsigned long long)searches);
@@ -285,7 +306,7 @@ hipError_t launch_init(const Plan &pl, const Work &w, const int64_t *d_offsets, 
 template <typename K>
 static hipError_t split_t(const void *data, const int64_t *offs, const Plan &pl, const Work &w,
                           int level, const MlpDev *mlp, hipStream_t s) {
-    int g = grid_for(pl.cap_nodes * 64, kSplitThreads, 4096);   // one wave per node
+    int g = grid_for(pl.cap_nodes, kSplitThreads, 2048);
     if (mlp)
         hipLaunchKernelGGL((k_split<K, true>), dim3(g), dim3(kSplitThreads), 0, s,
                            (const K *)data, offs, pl, w, level, mlp);
