@@ -100,17 +100,24 @@ __global__ __launch_bounds__(kRotThreads) void k_rotate(EK *__restrict__ keys, E
     int64_t nrot = (int64_t)(packed >> kRotCountShift);
     if (nrot > cap_rot) nrot = cap_rot;
     const int64_t nitems = (int64_t)(packed & kRotWorkMask);
+    if (nrot == 0 || nitems == 0) return;
+    // Grid-stride over the items; the descriptor of the previous item is
+    // reused while it still covers the current one (large exchanges).
+    Rot R;
+    R.w0 = 1;
+    R.nw = 0;        // empty: forces a search for the first item
     for (int64_t wi = blockIdx.x; wi < nitems; wi += gridDim.x) {
-        // exchange holding item wi: last r with rot[r].w0 <= wi
-        int64_t lo = 0, hi = nrot;
-        while (hi - lo > 1) {
-            int64_t mid = (lo + hi) >> 1;
-            if (rot[mid].w0 <= wi) lo = mid; else hi = mid;
+        if (wi < R.w0 || wi >= R.w0 + R.nw) {
+            // exchange holding item wi: last r with rot[r].w0 <= wi
+            int64_t lo = 0, hi = nrot;
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) >> 1;
+                if (rot[mid].w0 <= wi) lo = mid; else hi = mid;
+            }
+            R = rot[lo];
+            if (wi < R.w0 || wi >= R.w0 + R.nw) continue;   // a dropped exchange
         }
-        if (nrot == 0) break;
-        const Rot R = rot[lo];
         const int64_t local = wi - R.w0;
-        if (local < 0 || local >= R.nw) continue;
         do_item<EK>(keys, R, local, phase);
         if constexpr (!std::is_same<EV, NoVal>::value) do_item<EV>(vals, R, local, phase);
     }
