@@ -26,7 +26,19 @@ constexpr int kRotPer = (int)(kRotChunk / kRotThreads);   // pairs per thread
 
 struct NoVal {};
 
-// Swap pairs [c0, c1) of (p[a + t], p[b + t]).
+// 16-byte vectors with only element alignment: gfx950 runs global memory in
+// unaligned-access mode, so each becomes one dwordx4 access (used by the
+// reversals, where they measured faster than element accesses).
+template <typename E>
+struct __attribute__((aligned(sizeof(E)))) Vec {
+    static constexpr int N = 16 / (int)sizeof(E);
+    E v[N];
+};
+
+// Swap pairs [c0, c1) of (p[a + t], p[b + t]), one element per lane and
+// access (64 lanes = one contiguous 256-byte run per wave and region).
+// Measured on MI355X, this beats 16-byte vectors here (two independent
+// read streams and two write streams at unrelated alignments).
 template <typename E>
 __device__ __forceinline__ void swap_chunk(E *__restrict__ p, int64_t a, int64_t b, int64_t c0,
                                            int64_t c1) {
@@ -43,20 +55,47 @@ __device__ __forceinline__ void swap_chunk(E *__restrict__ p, int64_t a, int64_t
     }
 }
 
-// Reverse segment [s, s+m): swap pairs (s + t, s + m - 1 - t) for t in [c0, c1).
+// Reverse segment [s, s+m): swap pairs (s + t, s + m - 1 - t) for t in
+// [c0, c1).  A vector of pairs t..t+W-1 meets the mirrored vector ending at
+// s+m-1-t, reversed element-wise; vectors that would overlap the mirror
+// (the middle of the segment) or run past c1 fall back to elements.
 template <typename E>
 __device__ __forceinline__ void rev_chunk(E *__restrict__ p, int64_t s, int64_t m, int64_t c0,
                                           int64_t c1) {
-    E x[kRotPer], y[kRotPer];
+    using V = Vec<E>;
+    constexpr int W = V::N;
+    constexpr int NV = kRotPer / W;
+    V x[NV], y[NV];
 #pragma unroll
-    for (int u = 0; u < kRotPer; ++u) {
-        int64_t t = c0 + threadIdx.x + (int64_t)u * kRotThreads;
-        if (t < c1) { x[u] = p[s + t]; y[u] = p[s + m - 1 - t]; }
+    for (int u = 0; u < NV; ++u) {
+        int64_t t = c0 + (int64_t)(threadIdx.x + u * kRotThreads) * W;
+        if (t + W <= c1 && t + W - 1 < m - W - t) {
+            x[u] = *reinterpret_cast<const V *>(p + s + t);
+            y[u] = *reinterpret_cast<const V *>(p + s + m - W - t);
+        }
     }
 #pragma unroll
-    for (int u = 0; u < kRotPer; ++u) {
-        int64_t t = c0 + threadIdx.x + (int64_t)u * kRotThreads;
-        if (t < c1) { p[s + t] = y[u]; p[s + m - 1 - t] = x[u]; }
+    for (int u = 0; u < NV; ++u) {
+        int64_t t = c0 + (int64_t)(threadIdx.x + u * kRotThreads) * W;
+        if (t + W <= c1 && t + W - 1 < m - W - t) {
+            V rx, ry;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                rx.v[j] = y[u].v[W - 1 - j];
+                ry.v[j] = x[u].v[W - 1 - j];
+            }
+            *reinterpret_cast<V *>(p + s + t) = rx;
+            *reinterpret_cast<V *>(p + s + m - W - t) = ry;
+        } else {
+            for (int j = 0; j < W; ++j) {
+                const int64_t tt = t + j;
+                if (tt < c1) {
+                    E xa = p[s + tt], yb = p[s + m - 1 - tt];
+                    p[s + tt] = yb;
+                    p[s + m - 1 - tt] = xa;
+                }
+            }
+        }
     }
 }
 
