@@ -82,6 +82,8 @@ typedef struct {
     int64_t leaf_elems;      /* elements merged by the leaf merge (device)    */
     int64_t search_probes;   /* key-pair probes in all split searches (dev.)  */
     int64_t searches;        /* split searches performed (device)             */
+    int32_t leaf_config;     /* leaf-merge configuration used (0..2)           */
+    int32_t leaf_grid;       /* resident workgroups of the leaf merge          */
 } im_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -119,6 +121,59 @@ int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n,
 int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
                              int64_t total_elems, int64_t max_instance,
                              int key_dtype, int val_dtype, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Captured batched merge: the whole launch sequence of one batched merge  */
+/* (division levels of Alg. 3, exchanges of Sec. 3.4, per-pair merges)    */
+/* recorded once in a HIP graph and replayed with one call.               */
+/* ---------------------------------------------------------------------- */
+typedef struct im_graph im_graph;
+
+/* Record a batched merge of the given buffers into a new graph object.
+ * data, d_offsets: device pointers baked into the graph; the caller keeps
+ * ownership and must keep them alive until im_graph_destroy.  Between
+ * replays the caller may change the data and the offsets' contents, as long
+ * as n stays the same, d_offsets[2n] <= total_elems and every instance stays
+ * within max_instance (0: total_elems).  The graph owns a private workspace
+ * (allocated here), so replays do not touch the library's shared one; two
+ * replays of the same graph that overlap in time race.  Capture runs on a
+ * private stream; `stream` only orders the workspace set-up.  The leaf merge
+ * node is marked cooperative when the runtime accepts the attribute (queried
+ * by im_graph_cooperative).  IM_CHECK and stage profiling do not apply. */
+int batched_inplace_merge_graph(im_graph **out, void *data, const int64_t *d_offsets,
+                                int64_t n, int64_t total_elems, int64_t max_instance,
+                                int dtype, hipStream_t stream);
+/* Enqueue one replay on `stream`. */
+int im_graph_launch(im_graph *g, hipStream_t stream);
+/* 1 if the leaf merge node carries the cooperative attribute, else 0. */
+int im_graph_cooperative(const im_graph *g);
+/* Free the graph and its workspace (synchronises the device first). */
+int im_graph_destroy(im_graph *g);
+
+/* ---------------------------------------------------------------------- */
+/* Leaf-merge configuration and its autotuner (not part of the paper).     */
+/* ---------------------------------------------------------------------- */
+/* Configurations of the per-pair merge (workgroup threads x items per
+ * thread): 0 = 512 threads, large tiles (about 70 KB of LDS per tile);
+ * 1 = 256 threads, same items per thread; 2 = 256 threads, half the items. */
+#define IM_LEAF_CONFIGS 3
+
+/* Force a configuration for the calling process (0..IM_LEAF_CONFIGS-1), or
+ * -1 to return to automatic choice (tuned table, else configuration 0). */
+int inplace_merge_set_config(int cfg);
+
+/* Time every configuration on a private copy of the given batched input
+ * (data and d_offsets are only read) and remember the fastest one for this
+ * workload class: (device, key size, payload size, floor(log2(mean instance
+ * size))).  Later merges of that class use it unless a configuration is
+ * forced.  val_dtype: -1 for keys only.  reps >= 1 timed runs per
+ * configuration (plus one warm-up); ms_out (host, may be NULL) receives the
+ * median milliseconds per configuration; *chosen (may be NULL) the winner.
+ * Allocates and frees a scratch copy of the data; synchronises `stream`. */
+int inplace_merge_autotune(const void *data, const int64_t *d_offsets, int64_t n,
+                           int64_t total_elems, int64_t max_instance, int key_dtype,
+                           int val_dtype, int reps, double *ms_out, int *chosen,
+                           hipStream_t stream);
 
 /* In-place merge sort of data[0, n): each tile is sorted in LDS, then
  * bottom-up passes of the batched merge double the sorted run length; the

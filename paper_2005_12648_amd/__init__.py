@@ -25,6 +25,7 @@ __all__ = [
     "batched_inplace_merge", "batched_inplace_merge_kv", "inplace_merge_sort",
     "corank", "rotate", "fetch_stats", "workspace_bytes", "set_workspace",
     "MergeModel", "MLP_HIDDEN", "MLP_PARAMS", "profile", "profile_read", "STAGES",
+    "MergeGraph", "set_config", "autotune", "LEAF_CONFIGS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +34,7 @@ _lib = None
 
 MLP_HIDDEN = 32
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
+LEAF_CONFIGS = 3
 
 # im_dtype codes of the C ABI
 _DT = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3}
@@ -60,6 +62,7 @@ class _Stats(ctypes.Structure):
         ("rotations", ctypes.c_int64), ("rotated_elems", ctypes.c_int64),
         ("reversed_elems", ctypes.c_int64), ("leaf_elems", ctypes.c_int64),
         ("search_probes", ctypes.c_int64), ("searches", ctypes.c_int64),
+        ("leaf_config", ctypes.c_int32), ("leaf_grid", ctypes.c_int32),
     ]
 
 
@@ -106,6 +109,13 @@ def load():
         "merge_model_free": [vp],
         "inplace_merge_profile": [c_int],
         "inplace_merge_profile_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), c_int, vp],
+        "batched_inplace_merge_graph": [ctypes.POINTER(vp), vp, vp, i64, i64, i64, c_int, vp],
+        "im_graph_launch": [vp, vp],
+        "im_graph_cooperative": [vp],
+        "im_graph_destroy": [vp],
+        "inplace_merge_set_config": [c_int],
+        "inplace_merge_autotune": [vp, vp, i64, i64, i64, c_int, c_int, c_int,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -284,6 +294,78 @@ def set_workspace(buf: Optional[torch.Tensor]):
     with torch.cuda.device(buf.device):
         _check(load().inplace_merge_set_workspace(ctypes.c_void_p(buf.data_ptr()),
                                                   buf.numel() * buf.element_size()))
+
+
+class MergeGraph:
+    """A batched merge recorded once in a HIP graph and replayed by launch().
+
+    The data and offsets tensors are baked into the graph: keep them alive and
+    change only their contents between replays (same instance count, total at
+    most ``data.numel()``, every instance at most ``max_instance``)."""
+
+    def __init__(self, data: torch.Tensor, offsets: torch.Tensor, max_instance: int = 0,
+                 stream=None):
+        _dev_tensor(data, "data")
+        _dev_tensor(offsets, "offsets")
+        if offsets.dtype != torch.int64 or offsets.numel() < 3 or offsets.numel() % 2 != 1:
+            raise ValueError("offsets must be int64 with 2n+1 entries, n >= 1")
+        self._h = None
+        self._data, self._offsets = data, offsets
+        h = ctypes.c_void_p()
+        n = (offsets.numel() - 1) // 2
+        with torch.cuda.device(data.device):
+            _check(load().batched_inplace_merge_graph(
+                ctypes.byref(h), ctypes.c_void_p(data.data_ptr()),
+                ctypes.c_void_p(offsets.data_ptr()), n, data.numel(), max_instance,
+                _key_code(data), _stream(stream)))
+        self._h = h
+        self.device = data.device
+
+    @property
+    def cooperative(self) -> bool:
+        return bool(load().im_graph_cooperative(self._h))
+
+    def launch(self, stream=None):
+        with torch.cuda.device(self.device):
+            _check(load().im_graph_launch(self._h, _stream(stream)))
+        return self._data
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            with torch.cuda.device(self.device):
+                load().im_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_config(cfg: int):
+    """Force the leaf-merge configuration (0..LEAF_CONFIGS-1) or -1 for automatic."""
+    _check(load().inplace_merge_set_config(int(cfg)))
+
+
+def autotune(data: torch.Tensor, offsets: torch.Tensor, max_instance: int = 0,
+             vals_dtype: Optional[torch.dtype] = None, reps: int = 3, stream=None):
+    """Time every leaf configuration on a copy of this batched input and remember
+    the fastest for its workload class.  Returns (chosen, [median ms per config])."""
+    _dev_tensor(data, "data")
+    _dev_tensor(offsets, "offsets")
+    if offsets.dtype != torch.int64 or offsets.numel() < 3 or offsets.numel() % 2 != 1:
+        raise ValueError("offsets must be int64 with 2n+1 entries, n >= 1")
+    n = (offsets.numel() - 1) // 2
+    ms = (ctypes.c_double * LEAF_CONFIGS)()
+    chosen = ctypes.c_int(-1)
+    vcode = -1 if vals_dtype is None else _DT[vals_dtype]
+    with torch.cuda.device(data.device):
+        _check(load().inplace_merge_autotune(
+            ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+            data.numel(), max_instance, _key_code(data), vcode, reps, ms, ctypes.byref(chosen),
+            _stream(stream)))
+    return chosen.value, list(ms)
 
 
 class MergeModel:

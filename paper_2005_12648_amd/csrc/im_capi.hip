@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -92,7 +93,10 @@ struct DevState {
     size_t user_bytes = 0;
     hipEvent_t done = nullptr;   // last enqueued use of the workspace
     bool done_valid = false;
-    int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // leaf grid by (key 4/8, payload 0/4/8)
+    int grid[kLeafCfgs][2][3] = {};   // leaf grid by (config, key 4/8, payload 0/4/8)
+    // Autotuned leaf configuration by (key 4/8, payload 0/4/8, floor(log2 of
+    // the mean instance size)); -1: not tuned.
+    int tuned[2][3][64];
     int64_t *sort_off = nullptr; // offsets of the merge-sort passes
     int64_t sort_off_cap = 0;
     // Tile flags sit right after the counters.  flag_cap flags there are
@@ -100,7 +104,33 @@ struct DevState {
     // calls); the rest of the layout always starts after them.
     int64_t flag_cap = 0;
     uint32_t epoch = 0;
+    DevState() {
+        for (auto &a : tuned)
+            for (auto &b : a)
+                for (int &c : b) c = -1;
+    }
 };
+
+std::atomic<int> g_force_cfg{-1};   // inplace_merge_set_config
+
+int size_class(int64_t n_inst, int64_t total) {
+    int64_t mean = total / std::max<int64_t>(n_inst, 1);
+    int c = 0;
+    while (c < 63 && (int64_t(2) << c) <= mean) ++c;
+    return c;
+}
+
+int key_index(int ek) { return ek == 4 ? 0 : 1; }
+int val_index(int ev) { return ev == 0 ? 0 : (ev == 4 ? 1 : 2); }
+
+// Leaf configuration of a run: forced, else tuned for the class, else 0.
+int choose_cfg(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int override_cfg) {
+    if (override_cfg >= 0 && override_cfg < kLeafCfgs) return override_cfg;
+    int f = g_force_cfg.load();
+    if (f >= 0 && f < kLeafCfgs) return f;
+    int t = ds->tuned[key_index(ek)][val_index(ev)][size_class(n_inst, total)];
+    return (t >= 0 && t < kLeafCfgs) ? t : 0;
+}
 
 DevState g_dev[64];
 
@@ -115,15 +145,15 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Sizes and derived limits of one pipeline run.
 bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int64_t max_inst,
-               Plan *pl) {
-    int vi = ev == 0 ? 0 : (ev == 4 ? 1 : 2);
-    int ki = ek == 4 ? 0 : 1;
-    if (ds->grid[ki][vi] == 0) ds->grid[ki][vi] = leaf_grid(ek, ev);
-    int G = ds->grid[ki][vi];
+               int cfg, Plan *pl) {
+    const int vi = val_index(ev), ki = key_index(ek);
+    if (ds->grid[cfg][ki][vi] == 0) ds->grid[cfg][ki][vi] = leaf_grid(ek, ev, cfg);
+    int G = ds->grid[cfg][ki][vi];
     if (G <= 0) return false;
     int th, ipt;
     size_t lds;
-    leaf_geometry(ek, ev, &th, &ipt, &lds);
+    leaf_geometry(ek, ev, cfg, &th, &ipt, &lds);
+    pl->cfg = cfg;
     const char *cap_env = std::getenv("IM_LEAF_TILES");   // test hook: tiles per leaf cap
     int64_t tiles_per_leaf = G;
     if (cap_env) {
@@ -247,17 +277,65 @@ int read_error_bits(Counters *ctr, hipStream_t s, unsigned *bits) {
     return IM_OK;
 }
 
+// Everything up to the leaf merge: counters and roots, division levels,
+// leaf planning, tile co-ranks and dependencies.  `offs` is the caller's
+// offsets or null for a single pair (la, lb).
+int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
+                     int64_t n_inst, int64_t la, int64_t lb, const MlpDev *mlp, const Plan &pl,
+                     const Work &w, bool check, bool prof, hipStream_t s) {
+    const int ek = key_size(key_dt);
+    IM_HIP(launch_init(pl, w, d_offsets, la, lb, s), "launch init");
+    const int64_t *offs = d_offsets ? d_offsets : w.offsets1;
+    if (check) {
+        IM_HIP(launch_check_sorted(key_dt, keys, offs, n_inst, w.ctr, s), "launch check");
+        unsigned bits = 0;
+        int rc = read_error_bits(w.ctr, s, &bits);
+        if (rc) return rc;
+        if (bits & kErrOffsets) return fail(IM_ERR_INVALID_ARG, "offsets are not monotone");
+        if (bits & kErrNotSorted) return fail(IM_ERR_NOT_SORTED, "an input run is not ascending");
+    }
+    for (int lv = 0; lv < pl.max_levels; ++lv) {
+        hipEvent_t e0 = prof ? prof_begin(s) : nullptr;
+        IM_HIP(launch_split(key_dt, keys, offs, pl, w, lv, mlp, s), "launch split");
+        prof_end(e0, kStSplit, 1, s);
+        hipEvent_t e1 = prof ? prof_begin(s) : nullptr;
+        IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 0, s), "launch rotate A");
+        IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");
+        prof_end(e1, kStRotate, 2, s);
+    }
+    hipEvent_t e2 = prof ? prof_begin(s) : nullptr;
+    IM_HIP(launch_plan(pl, w, s), "launch plan");
+    prof_end(e2, kStPlan, 1, s);
+    hipEvent_t e3 = prof ? prof_begin(s) : nullptr;
+    IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
+    IM_HIP(launch_tiledeps(pl, w, s), "launch tile dependencies");
+    prof_end(e3, kStTileRank, 2, s);
+    return IM_OK;
+}
+
+void record_stats(const Plan &pl, const Work &w) {
+    g_stats = im_stats{};
+    g_stats.leaf_capacity = pl.leaf_cap;
+    g_stats.tile = pl.tile;
+    g_stats.max_levels = pl.max_levels;
+    g_stats.leaf_config = pl.cfg;
+    g_stats.leaf_grid = pl.grid_leaf;
+    g_last_ctr = w.ctr;
+}
+
 // The whole merge: division levels, leaf planning, tile co-ranks, leaf merge.
+// cfg_override >= 0 forces a leaf configuration (autotuner).
 int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
                  int64_t n_inst, int64_t total, int64_t max_inst, int64_t la, int64_t lb,
-                 const MlpDev *mlp, hipStream_t s) {
+                 const MlpDev *mlp, hipStream_t s, int cfg_override = -1) {
     int dev = 0;
     DevState *ds = dev_state(&dev);
     if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
     std::lock_guard<std::mutex> lock(ds->mu);
     const int ek = key_size(key_dt);
+    const int cfg = choose_cfg(ds, ek, ev, n_inst, total, cfg_override);
     Plan pl;
-    if (!make_plan(ds, ek, ev, n_inst, total, max_inst, &pl))
+    if (!make_plan(ds, ek, ev, n_inst, total, max_inst, cfg, &pl))
         return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
     size_t need = carve(pl, ds->flag_cap, nullptr, nullptr);
     void *base = nullptr;
@@ -287,44 +365,17 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     const bool check = checked_mode();
     if (std::getenv("IM_FAULT") && std::strcmp(std::getenv("IM_FAULT"), "launch") == 0)
         return fail(IM_ERR_HIP, "kernel launch failed (injected)");
-    IM_HIP(launch_init(pl, w, d_offsets, la, lb, s), "launch init");
-    const int64_t *offs = d_offsets ? d_offsets : w.offsets1;
-    if (check) {
-        IM_HIP(launch_check_sorted(key_dt, keys, offs, n_inst, w.ctr, s), "launch check");
-        unsigned bits = 0;
-        rc = read_error_bits(w.ctr, s, &bits);
-        if (rc) return rc;
-        if (bits & kErrOffsets) return fail(IM_ERR_INVALID_ARG, "offsets are not monotone");
-        if (bits & kErrNotSorted) return fail(IM_ERR_NOT_SORTED, "an input run is not ascending");
-    }
     const bool prof = g_prof && !stream_capturing(s);
-    for (int lv = 0; lv < pl.max_levels; ++lv) {
-        hipEvent_t e0 = prof ? prof_begin(s) : nullptr;
-        IM_HIP(launch_split(key_dt, keys, offs, pl, w, lv, mlp, s), "launch split");
-        prof_end(e0, kStSplit, 1, s);
-        hipEvent_t e1 = prof ? prof_begin(s) : nullptr;
-        IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 0, s), "launch rotate A");
-        IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");
-        prof_end(e1, kStRotate, 2, s);
-    }
-    hipEvent_t e2 = prof ? prof_begin(s) : nullptr;
-    IM_HIP(launch_plan(pl, w, s), "launch plan");
-    prof_end(e2, kStPlan, 1, s);
-    hipEvent_t e3 = prof ? prof_begin(s) : nullptr;
-    IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
-    IM_HIP(launch_tiledeps(pl, w, s), "launch tile dependencies");
-    prof_end(e3, kStTileRank, 2, s);
+    rc = enqueue_division(key_dt, ev, keys, vals, d_offsets, n_inst, la, lb, mlp, pl, w, check,
+                          prof, s);
+    if (rc) return rc;
     hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
     IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
     prof_end(e4, kStLeafMerge, 1, s);
     rc = ws_leave(ds, s);
     if (rc) return rc;
 
-    g_stats = im_stats{};
-    g_stats.leaf_capacity = pl.leaf_cap;
-    g_stats.tile = pl.tile;
-    g_stats.max_levels = pl.max_levels;
-    g_last_ctr = w.ctr;
+    record_stats(pl, w);
     if (check) {
         unsigned bits = 0;
         rc = read_error_bits(w.ctr, s, &bits);
@@ -345,6 +396,17 @@ int check_common(const void *p, int64_t la, int64_t lb, int dt) {
 }
 
 }  // namespace
+
+// Captured batched merge: the executable graph and its private workspace.
+struct im_graph {
+    int device = 0;
+    Plan plan = {};
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool coop = false;
+};
 
 // ---------------------------------------------------------------------------
 // Learned model object.
@@ -465,16 +527,18 @@ size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dt
     DevState *ds = dev_state(nullptr);
     if (!ds) return 0;
     std::lock_guard<std::mutex> lock(ds->mu);
-    Plan pl;
-    if (!make_plan(ds, key_size(dtype), 8, std::max<int64_t>(n_inst, 1), std::max<int64_t>(total_elems, 1),
-                   0, &pl))
-        return 0;
-    size_t a = carve(pl, 0, nullptr, nullptr);
-    Plan pl2;
-    if (!make_plan(ds, key_size(dtype), 0, std::max<int64_t>(n_inst, 1),
-                   std::max<int64_t>(total_elems, 1), 0, &pl2))
-        return 0;
-    return std::max(a, carve(pl2, 0, nullptr, nullptr));
+    // the largest need over payload sizes and leaf configurations
+    size_t need = 0;
+    for (int cfg = 0; cfg < kLeafCfgs; ++cfg) {
+        for (int ev : {0, 4, 8}) {
+            Plan pl;
+            if (!make_plan(ds, key_size(dtype), ev, std::max<int64_t>(n_inst, 1),
+                           std::max<int64_t>(total_elems, 1), 0, cfg, &pl))
+                return 0;
+            need = std::max(need, carve(pl, 0, nullptr, nullptr));
+        }
+    }
+    return need;
 }
 
 int inplace_merge_set_workspace(void *d_ws, size_t bytes) {
@@ -554,6 +618,235 @@ int im_rotate(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t st
     if (lx == 0 || ly == 0) return IM_OK;
     if (!data) return fail(IM_ERR_INVALID_ARG, "null data pointer");
     IM_HIP(launch_rotate_single(data, lx, ly, elem_bytes, stream), "launch rotate");
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Captured batched merge.
+// ---------------------------------------------------------------------------
+int batched_inplace_merge_graph(im_graph **out, void *data, const int64_t *d_offsets, int64_t n,
+                                int64_t total_elems, int64_t max_instance, int dtype,
+                                hipStream_t stream) {
+    if (!out) return fail(IM_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    if (!valid_dtype(dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (n <= 0 || total_elems <= 0 || max_instance < 0)
+        return fail(IM_ERR_INVALID_ARG, "a graph needs n > 0 and total_elems > 0");
+    if (data == nullptr || d_offsets == nullptr) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (n >= (int64_t(1) << 31)) return fail(IM_ERR_INVALID_ARG, "too many instances");
+    DevState *ds = dev_state(nullptr);
+    if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    const int ek = key_size(dtype);
+    Plan pl;
+    {
+        std::lock_guard<std::mutex> lock(ds->mu);
+        const int cfg = choose_cfg(ds, ek, 0, n, total_elems, -1);
+        if (!make_plan(ds, ek, 0, n, total_elems, max_instance, cfg, &pl))
+            return fail(IM_ERR_HIP, "could not size the leaf merge grid");
+    }
+    pl.epoch = 1;   // every replay clears the flags first
+    im_graph *g = new (std::nothrow) im_graph();
+    if (!g) return fail(IM_ERR_WORKSPACE, "out of host memory");
+    (void)hipGetDevice(&g->device);
+    g->plan = pl;
+    g->ws_bytes = carve(pl, 0, nullptr, nullptr);
+    if (hipMalloc(&g->ws, g->ws_bytes) != hipSuccess) {
+        g->ws = nullptr;
+        im_graph_destroy(g);
+        return fail(IM_ERR_WORKSPACE, "graph workspace allocation failed");
+    }
+    Work w;
+    carve(pl, 0, g->ws, &w);
+    int th, ipt;
+    size_t lds;
+    leaf_geometry(ek, 0, pl.cfg, &th, &ipt, &lds);
+    const void *leaf_fn = leaf_kernel_ptr(dtype, 0, pl.cfg);
+    hipError_t e = leaf_fn ? hipFuncSetAttribute(leaf_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds)
+                           : hipErrorInvalidValue;
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    // the caller's stream may still be writing the inputs: order the capture
+    // stream's (non-captured) set-up after it
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        if (cs) (void)hipStreamDestroy(cs);
+        im_graph_destroy(g);
+        return hip_fail(e, "graph set-up");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    int rc = IM_OK;
+    if (e == hipSuccess) {
+        e = launch_fill32(w.tile_flag, pl.cap_tiles, 0u, cs);
+        if (e == hipSuccess)
+            rc = enqueue_division(dtype, 0, data, nullptr, d_offsets, n, 0, 0, nullptr, pl, w,
+                                  false, false, cs);
+    }
+    // the leaf merge is added by hand after the captured chain so that it can
+    // carry the cooperative attribute
+    std::vector<hipGraphNode_t> deps;
+    if (e == hipSuccess && rc == IM_OK) {
+        hipStreamCaptureStatus st;
+        unsigned long long id = 0;
+        hipGraph_t cg = nullptr;
+        const hipGraphNode_t *dp = nullptr;
+        size_t nd = 0;
+        e = hipStreamGetCaptureInfo_v2(cs, &st, &id, &cg, &dp, &nd);
+        if (e == hipSuccess) deps.assign(dp, dp + nd);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e_end = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc != IM_OK || e != hipSuccess || e_end != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        im_graph_destroy(g);
+        if (rc != IM_OK) return rc;
+        return hip_fail(e != hipSuccess ? e : e_end, "graph capture");
+    }
+    g->graph = graph;
+    void *keys = data, *vals = nullptr;
+    Plan plc = pl;
+    Work wc = w;
+    void *args[] = {&keys, &vals, &plc, &wc};
+    hipKernelNodeParams kp = {};
+    kp.func = const_cast<void *>(leaf_fn);
+    kp.gridDim = dim3(pl.grid_leaf);
+    kp.blockDim = dim3(th);
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t leaf_node = nullptr;
+    e = hipGraphAddKernelNode(&leaf_node, graph, deps.empty() ? nullptr : deps.data(), deps.size(),
+                              &kp);
+    if (e != hipSuccess) {
+        im_graph_destroy(g);
+        return hip_fail(e, "graph leaf node");
+    }
+    hipKernelNodeAttrValue av;
+    std::memset(&av, 0, sizeof(av));
+    av.cooperative = 1;
+    g->coop = hipGraphKernelNodeSetAttribute(leaf_node, hipKernelNodeAttributeCooperative, &av) ==
+              hipSuccess;
+    (void)hipGetLastError();   // an unsupported attribute leaves no sticky error
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        g->exec = nullptr;
+        im_graph_destroy(g);
+        return hip_fail(e, "graph instantiate");
+    }
+    record_stats(pl, w);
+    g_last_ctr = nullptr;   // counters live in the graph's workspace
+    *out = g;
+    g_err.clear();
+    return IM_OK;
+}
+
+int im_graph_launch(im_graph *g, hipStream_t stream) {
+    if (!g || !g->exec) return fail(IM_ERR_INVALID_ARG, "null graph");
+    IM_HIP(hipGraphLaunch(g->exec, stream), "graph launch");
+    g_stats = im_stats{};
+    g_stats.leaf_capacity = g->plan.leaf_cap;
+    g_stats.tile = g->plan.tile;
+    g_stats.max_levels = g->plan.max_levels;
+    g_stats.leaf_config = g->plan.cfg;
+    g_stats.leaf_grid = g->plan.grid_leaf;
+    g_last_ctr = reinterpret_cast<Counters *>(g->ws);   // first carve slot
+    return IM_OK;
+}
+
+int im_graph_cooperative(const im_graph *g) { return (g && g->coop) ? 1 : 0; }
+
+int im_graph_destroy(im_graph *g) {
+    if (!g) return IM_OK;
+    (void)hipDeviceSynchronize();
+    if (g_last_ctr == reinterpret_cast<Counters *>(g->ws)) g_last_ctr = nullptr;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ws) (void)hipFree(g->ws);
+    delete g;
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Leaf configuration and autotuner.
+// ---------------------------------------------------------------------------
+int inplace_merge_set_config(int cfg) {
+    if (cfg < -1 || cfg >= kLeafCfgs) return fail(IM_ERR_INVALID_ARG, "no such leaf configuration");
+    g_force_cfg.store(cfg);
+    return IM_OK;
+}
+
+int inplace_merge_autotune(const void *data, const int64_t *d_offsets, int64_t n,
+                           int64_t total_elems, int64_t max_instance, int key_dtype,
+                           int val_dtype, int reps, double *ms_out, int *chosen,
+                           hipStream_t stream) {
+    if (!valid_dtype(key_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (val_dtype != -1 && !valid_dtype(val_dtype))
+        return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported payload dtype");
+    if (n <= 0 || total_elems <= 0 || max_instance < 0 || reps < 1)
+        return fail(IM_ERR_INVALID_ARG, "autotune needs n > 0, total_elems > 0, reps >= 1");
+    if (!data || !d_offsets) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (n >= (int64_t(1) << 31)) return fail(IM_ERR_INVALID_ARG, "too many instances");
+    DevState *ds = dev_state(nullptr);
+    if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    const int ek = key_size(key_dtype);
+    const int ev = val_dtype < 0 ? 0 : key_size(val_dtype);
+    // the data buffer holds exactly d_offsets[2n] elements
+    int64_t used = 0;
+    IM_HIP(hipStreamSynchronize(stream), "autotune sync");
+    IM_HIP(hipMemcpy(&used, d_offsets + 2 * n, sizeof(used), hipMemcpyDeviceToHost),
+           "read offsets");
+    if (used < 0 || used > total_elems)
+        return fail(IM_ERR_INVALID_ARG, "d_offsets[2n] outside [0, total_elems]");
+    void *sk = nullptr, *sv = nullptr;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(stream);
+        if (sk) (void)hipFree(sk);
+        if (sv) (void)hipFree(sv);
+        if (ea) (void)hipEventDestroy(ea);
+        if (eb) (void)hipEventDestroy(eb);
+    };
+    const size_t nb = (size_t)std::max<int64_t>(used, 1);
+    if (hipMalloc(&sk, nb * ek) != hipSuccess || (ev && hipMalloc(&sv, nb * ev) != hipSuccess)) {
+        cleanup();
+        return fail(IM_ERR_WORKSPACE, "autotune scratch allocation failed");
+    }
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+        cleanup();
+        return fail(IM_ERR_HIP, "event create");
+    }
+    if (ev) (void)hipMemsetAsync(sv, 0, nb * ev, stream);
+    double med[kLeafCfgs];
+    int best = 0;
+    for (int cfg = 0; cfg < kLeafCfgs; ++cfg) {
+        std::vector<double> t;
+        for (int r = 0; r <= reps; ++r) {
+            hipError_t e = hipMemcpyAsync(sk, data, (size_t)used * ek, hipMemcpyDeviceToDevice, stream);
+            if (e == hipSuccess) e = hipEventRecord(ea, stream);
+            if (e != hipSuccess) { cleanup(); return hip_fail(e, "autotune copy"); }
+            int rc = run_pipeline(key_dtype, ev, sk, sv, d_offsets, n, total_elems, max_instance,
+                                  0, 0, nullptr, stream, cfg);
+            if (rc) { cleanup(); return rc; }
+            e = hipEventRecord(eb, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(eb);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+            if (e != hipSuccess) { cleanup(); return hip_fail(e, "autotune timing"); }
+            if (r > 0) t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        med[cfg] = t[t.size() / 2];
+        if (ms_out) ms_out[cfg] = med[cfg];
+        if (med[cfg] < med[best]) best = cfg;
+    }
+    cleanup();
+    {
+        std::lock_guard<std::mutex> lock(ds->mu);
+        ds->tuned[key_index(ek)][val_index(ev)][size_class(n, total_elems)] = best;
+    }
+    if (chosen) *chosen = best;
+    g_err.clear();
     return IM_OK;
 }
 

@@ -100,8 +100,10 @@ struct Plan {
     int32_t grid_leaf;      // persistent grid of the leaf merge
     int64_t cap_nodes, cap_rot, cap_leaves, cap_tiles;
     uint32_t epoch;         // value a tile writes to its "inputs read" flag
-    uint32_t pad;
+    int32_t cfg;            // leaf-merge configuration (tile size per workgroup)
 };
+
+constexpr int kLeafCfgs = 3;   // leaf-merge tile configurations (im_leaf.hip)
 
 // Workspace carve-up (device pointers).
 struct Work {
@@ -134,10 +136,10 @@ hipError_t launch_leafmerge(int key, int esize_v, void *keys, void *vals, const 
                             const Work &w, hipStream_t s);
 hipError_t launch_tiledeps(const Plan &pl, const Work &w, hipStream_t s);
 hipError_t launch_fill32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
-// Tile geometry of the leaf merge for a (key size, payload size) pair.
-void leaf_geometry(int esize_k, int esize_v, int *threads, int *ipt, size_t *lds_bytes);
-int leaf_grid(int esize_k, int esize_v);   // persistent grid (resident workgroups)
-const void *leaf_kernel_ptr(int key, int esize_v);
+// Tile geometry of the leaf merge for a (key size, payload size, config).
+void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, size_t *lds_bytes);
+int leaf_grid(int esize_k, int esize_v, int cfg);   // persistent grid (resident workgroups)
+const void *leaf_kernel_ptr(int key, int esize_v, int cfg);
 
 hipError_t launch_corank(int key, const void *data, int64_t la, int64_t lb, const int64_t *d_k,
                          int64_t nk, int64_t *d_out, const MlpDev *mlp, int32_t *d_probes,

@@ -408,47 +408,51 @@ hipError_t launch_plan(const Plan &pl, const Work &w, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ---- geometry and dispatch ------------------------------------------------
-template <typename K, typename V, int THREADS, int IPT>
-struct LeafCfg {
-    static constexpr int T = THREADS * IPT;
-    static size_t lds() {
-        return (size_t)LdsPad<T>::elems * sizeof(K) +
-               (std::is_same<V, NoValL>::value ? 0 : (size_t)LdsPad<T>::elems * sizeof(V));
-    }
-    static const void *fn() { return (const void *)&k_leafmerge<K, V, THREADS, IPT>; }
-};
+// ---- geometry and dispatch ----------------------------------------------
+// (key bytes, payload bytes, config) -> (threads, items per thread).  Items
+// per thread are odd, so the blocked LDS accesses are bank-conflict free.
+//   config 0: 8 waves per tile, about 70 KB of LDS (two workgroups fill a CU)
+//   config 1: 4 waves per tile, same items per thread (half the tile, four
+//             workgroups per CU): finer granularity for many small instances
+//   config 2: 4 waves per tile, half the items per thread (quarter tile)
+// The tiles resident on the chip bound how far a leaf may move elements, so
+// the smaller tiles trade shorter pipelines for more division levels on
+// large merges; the autotuner measures the trade per workload class.
+static int ipt_big(int eb) { return eb <= 4 ? 35 : (eb <= 8 ? 17 : (eb <= 12 ? 11 : 9)); }
+static int ipt_small(int eb) { return eb <= 4 ? 17 : (eb <= 8 ? 9 : 5); }
 
-// (key bytes, payload bytes) -> (threads, items per thread).  Items per
-// thread are odd and sized so that a tile takes about 70 KB of LDS: two
-// workgroups fill a CU's LDS, and the tiles resident on the whole chip --
-// which bound how far a leaf may move its elements -- hold about 40 MB.
-static void geom(int ek, int ev, int *th, int *ipt) {
-    *th = 512;
+static void geom(int ek, int ev, int cfg, int *th, int *ipt) {
     const int eb = ek + ev;
-    *ipt = eb <= 4 ? 35 : (eb <= 8 ? 17 : (eb <= 12 ? 11 : 9));
+    *th = cfg == 0 ? 512 : 256;
+    *ipt = cfg == 2 ? ipt_small(eb) : ipt_big(eb);
 }
 
-void leaf_geometry(int esize_k, int esize_v, int *threads, int *ipt, size_t *lds_bytes) {
-    geom(esize_k, esize_v, threads, ipt);
+void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, size_t *lds_bytes) {
+    geom(esize_k, esize_v, cfg, threads, ipt);
     int T = *threads * *ipt;
     size_t pe = (size_t)(T + 2);
     *lds_bytes = pe * esize_k + pe * esize_v;
 }
 
+// One line per (key, payload): the three configurations' (threads, items).
+#define IM_LEAF_KV(X, K, V, BIG, SMALL) \
+    X(K, V, 0, 512, BIG)                \
+    X(K, V, 1, 256, BIG)                \
+    X(K, V, 2, 256, SMALL)
+
 #define IM_LEAF_CASES(X)                        \
-    X(int32_t, NoValL, 512, 35)                 \
-    X(uint32_t, NoValL, 512, 35)                \
-    X(int64_t, NoValL, 512, 17)                 \
-    X(uint64_t, NoValL, 512, 17)                \
-    X(int32_t, uint32_t, 512, 17)               \
-    X(uint32_t, uint32_t, 512, 17)              \
-    X(int64_t, uint32_t, 512, 11)               \
-    X(uint64_t, uint32_t, 512, 11)              \
-    X(int32_t, uint64_t, 512, 11)               \
-    X(uint32_t, uint64_t, 512, 11)              \
-    X(int64_t, uint64_t, 512, 9)                \
-    X(uint64_t, uint64_t, 512, 9)
+    IM_LEAF_KV(X, int32_t, NoValL, 35, 17)      \
+    IM_LEAF_KV(X, uint32_t, NoValL, 35, 17)     \
+    IM_LEAF_KV(X, int64_t, NoValL, 17, 9)       \
+    IM_LEAF_KV(X, uint64_t, NoValL, 17, 9)      \
+    IM_LEAF_KV(X, int32_t, uint32_t, 17, 9)     \
+    IM_LEAF_KV(X, uint32_t, uint32_t, 17, 9)    \
+    IM_LEAF_KV(X, int64_t, uint32_t, 11, 5)     \
+    IM_LEAF_KV(X, uint64_t, uint32_t, 11, 5)    \
+    IM_LEAF_KV(X, int32_t, uint64_t, 11, 5)     \
+    IM_LEAF_KV(X, uint32_t, uint64_t, 11, 5)    \
+    IM_LEAF_KV(X, int64_t, uint64_t, 9, 5)      \
+    IM_LEAF_KV(X, uint64_t, uint64_t, 9, 5)
 
 template <typename K> struct KeyOf;
 template <> struct KeyOf<int32_t> { static constexpr int code = kI32; };
@@ -458,21 +462,21 @@ template <> struct KeyOf<uint64_t> { static constexpr int code = kU64; };
 template <typename V> struct ValSize { static constexpr int v = sizeof(V); };
 template <> struct ValSize<NoValL> { static constexpr int v = 0; };
 
-const void *leaf_kernel_ptr(int key, int esize_v) {
-#define X(K, V, TH, IPT)                                                     \
-    if (KeyOf<K>::code == key && ValSize<V>::v == esize_v)                   \
-        return LeafCfg<K, V, TH, IPT>::fn();
+const void *leaf_kernel_ptr(int key, int esize_v, int cfg) {
+#define X(K, V, C, TH, IPT)                                                      \
+    if (KeyOf<K>::code == key && ValSize<V>::v == esize_v && C == cfg)         \
+        return (const void *)&k_leafmerge<K, V, TH, IPT>;
     IM_LEAF_CASES(X)
 #undef X
     return nullptr;
 }
 
-int leaf_grid(int esize_k, int esize_v) {
+int leaf_grid(int esize_k, int esize_v, int cfg) {
     int th, ipt;
     size_t lds;
-    leaf_geometry(esize_k, esize_v, &th, &ipt, &lds);
+    leaf_geometry(esize_k, esize_v, cfg, &th, &ipt, &lds);
     int key = esize_k == 4 ? kI32 : kI64;
-    const void *fn = leaf_kernel_ptr(key, esize_v);
+    const void *fn = leaf_kernel_ptr(key, esize_v, cfg);
     if (!fn) return 0;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
@@ -490,8 +494,8 @@ hipError_t launch_leafmerge(int key, int esize_v, void *keys, void *vals, const 
     int th, ipt;
     size_t lds;
     int esize_k = (key == kI32 || key == kU32) ? 4 : 8;
-    leaf_geometry(esize_k, esize_v, &th, &ipt, &lds);
-    const void *fn = leaf_kernel_ptr(key, esize_v);
+    leaf_geometry(esize_k, esize_v, pl.cfg, &th, &ipt, &lds);
+    const void *fn = leaf_kernel_ptr(key, esize_v, pl.cfg);
     if (!fn) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

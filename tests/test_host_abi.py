@@ -63,6 +63,23 @@ def test_validation_codes_without_device_work():
     assert lib.inplace_merge_sort(fake, -3, 0, None) == -1
     assert lib.im_rotate(fake, 3, 4, 3, None) == -2
     assert lib.im_corank(fake, 3, 3, 0, None, 5, None, None, None) == -1
+    # captured graph, leaf configuration and autotuner entry points
+    out = vp()
+    assert lib.batched_inplace_merge_graph(None, fake, fake, 4, 100, 0, 0, None) == -1
+    assert lib.batched_inplace_merge_graph(ctypes.byref(out), fake, fake, 4, 100, 0, 9, None) == -2
+    assert lib.batched_inplace_merge_graph(ctypes.byref(out), fake, fake, 0, 100, 0, 0, None) == -1
+    assert lib.batched_inplace_merge_graph(ctypes.byref(out), None, fake, 4, 100, 0, 0, None) == -1
+    assert out.value is None
+    assert lib.im_graph_launch(None, None) == -1
+    assert lib.im_graph_cooperative(None) == 0
+    assert lib.im_graph_destroy(None) == 0
+    assert lib.inplace_merge_set_config(3) == -1
+    assert lib.inplace_merge_set_config(-2) == -1
+    assert lib.inplace_merge_set_config(-1) == 0
+    assert lib.inplace_merge_autotune(fake, fake, 4, 100, 0, 9, -1, 3, None, None, None) == -2
+    assert lib.inplace_merge_autotune(fake, fake, 4, 100, 0, 0, 7, 3, None, None, None) == -2
+    assert lib.inplace_merge_autotune(fake, fake, 4, 100, 0, 0, -1, 0, None, None, None) == -1
+    assert lib.inplace_merge_autotune(None, fake, 4, 100, 0, 0, -1, 3, None, None, None) == -1
     # empty work is a successful no-op that touches nothing
     assert lib.inplace_merge(None, 0, 0, 0, None) == 0
     assert lib.inplace_merge(fake, 0, 7, 0, None) == 0
