@@ -162,10 +162,15 @@ def bench_headline(torch, im, oracle, gen, dev, args):
     n = la + lb
     log("c2: generating int32 2^27 + 2^27 on the device")
     pristine = gen.torch_pair_uniform(la, lb, SEED + 20, dev)
+    # leaf configuration chosen by the autotuner (outside the timed region)
+    off1 = torch.tensor([0, la, n], dtype=torch.int64, device=dev)
+    chosen, tune_ms = im.autotune(pristine, off1, reps=3)
+    log("c2: autotune ms per config", ["%.3f" % m for m in tune_ms], "chosen", chosen)
     ms, prof, bufs = timed_merges(torch, im, pristine, la, args.steps, args.warmup, profile=True)
     stats = im.fetch_stats()
     log("c2: %.3f ms/step, %.1f Gelem/s" % (ms, n / ms / 1e6))
-    res = {"ms": ms, "prof": prof, "stats": stats, "n": n}
+    res = {"ms": ms, "prof": prof, "stats": stats, "n": n,
+           "tune_ms": [round(m, 4) for m in tune_ms]}
     cpu = None
     if not args.no_cpu:
         host = pristine.cpu().numpy()
@@ -215,13 +220,47 @@ def bench_variant(torch, im, oracle, gen, dev, name, steps):
             "ms": round(ms, 4), "mismatches": bad}
 
 
+def event_timed(torch, pristine, buf, fn, reps):
+    """Median ms of fn() over reps runs, each on a fresh copy of pristine in buf
+    (copies outside the timed events)."""
+    ts = []
+    for _ in range(reps):
+        buf.copy_(pristine)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 def bench_batched(torch, im, oracle, gen, dev, steps):
     log("c4: generating 4096 instances")
     data, off_d, off = gen.torch_batch(4096, SEED + 40, dev)
     total = int(off[-1])
     max_inst = int(np.max(off[2::2] - off[0:-1:2]))
+    # autotuner: every leaf configuration timed on a copy, winner remembered
+    chosen, tune_ms = im.autotune(data, off_d, max_instance=max_inst, reps=3)
+    log("c4: autotune ms per config", ["%.3f" % m for m in tune_ms], "chosen", chosen)
     fn = lambda b: im.batched_inplace_merge(b, off_d, max_instance=max_inst)
     ms_b, _, bufs = timed_merges(torch, im, data, 0, steps, 1, fn=fn)
+    used_cfg = im.fetch_stats()["leaf_config"]
+    # the same merge recorded once in a HIP graph, replayed on fresh copies
+    gbuf = data.clone()
+    graph = im.MergeGraph(gbuf, off_d, max_instance=max_inst)
+    coop = graph.cooperative
+    event_timed(torch, data, gbuf, graph.launch, 1)                 # warm
+    ms_g = event_timed(torch, data, gbuf, graph.launch, max(steps, 3))
+    ebuf = data.clone()
+    ms_e = event_timed(torch, data, ebuf, lambda: fn(ebuf), max(steps, 3))
+    graph.launch()
+    torch.cuda.synchronize()
+    got_g = gbuf.cpu().numpy()
+    graph.close()
+    del gbuf, ebuf
     # the same 4096 instances as separate plain calls on one stream
     loop_buf = data.clone()
 
@@ -236,18 +275,24 @@ def bench_batched(torch, im, oracle, gen, dev, steps):
     host = data.cpu().numpy()
     got_b = bufs[0].cpu().numpy()
     got_p = loop_buf.cpu().numpy()
-    bad_b = bad_p = 0
+    bad_b = bad_p = bad_g = 0
     for q in range(4096):
         o0, o1, o2 = off[2 * q], off[2 * q + 1], off[2 * q + 2]
         want = oracle.merge(host[o0:o2], int(o1 - o0))
         bad_b += int(np.count_nonzero(got_b[o0:o2] != want))
         bad_p += int(np.count_nonzero(got_p[o0:o2] != want))
-    log("c4: batched %.3f ms, plain loop %.3f ms" % (ms_b, ms_p))
+        bad_g += int(np.count_nonzero(got_g[o0:o2] != want))
+    log("c4: batched %.3f ms, graph %.3f ms (eager per-call %.3f), plain loop %.3f ms"
+        % (ms_b, ms_g, ms_e, ms_p))
     return {"workload": "4096 instances, L_A, L_B ~ round(2^U[6,20]) int32, %d elements" % total,
             "batched_gelem_s": round(total / ms_b / 1e6, 2), "batched_ms": round(ms_b, 4),
+            "leaf_config": used_cfg, "autotune_ms_per_config": [round(m, 4) for m in tune_ms],
+            "graph_ms": round(ms_g, 4), "graph_gelem_s": round(total / ms_g / 1e6, 2),
+            "eager_single_call_ms": round(ms_e, 4), "graph_leaf_node_cooperative": coop,
             "plain_loop_gelem_s": round(total / ms_p / 1e6, 2), "plain_loop_ms": round(ms_p, 3),
             "speedup_vs_plain_loop": round(ms_p / ms_b, 2),
-            "mismatches_batched": bad_b, "mismatches_plain_loop": bad_p}
+            "mismatches_batched": bad_b, "mismatches_graph": bad_g,
+            "mismatches_plain_loop": bad_p}
 
 
 def bench_sort(torch, im, oracle, gen, dev):
@@ -357,7 +402,9 @@ def main():
         "config": {"workload": "c2: int32 in-place merge, L_A=L_B=2^27, runs uniform in [0,2^31) "
                                "each sorted", "elements": n,
                    "levels_used": st["levels_used"], "leaves": st["leaves"],
-                   "leaf_capacity": st["leaf_capacity"], "tile": st["tile"]},
+                   "leaf_capacity": st["leaf_capacity"], "tile": st["tile"],
+                   "leaf_config": st["leaf_config"], "leaf_grid": st["leaf_grid"],
+                   "autotune_ms_per_config": head["tune_ms"]},
         "effective_hbm_gb_s": round(2 * 4 * n / head["ms"] / 1e6, 1),
         "effective_hbm_frac": round(2 * 4 * n / head["ms"] / 1e6 / HBM_PEAK_GBS, 4),
         "mismatches": head.get("mismatch"),

@@ -82,7 +82,7 @@ typedef struct {
     int64_t leaf_elems;      /* elements merged by the leaf merge (device)    */
     int64_t search_probes;   /* key-pair probes in all split searches (dev.)  */
     int64_t searches;        /* split searches performed (device)             */
-    int32_t leaf_config;     /* leaf-merge configuration used (0..2)           */
+    int32_t leaf_config;     /* leaf-merge configuration used (0..3)           */
     int32_t leaf_grid;       /* resident workgroups of the leaf merge          */
 } im_stats;
 
@@ -153,10 +153,15 @@ int im_graph_destroy(im_graph *g);
 /* ---------------------------------------------------------------------- */
 /* Leaf-merge configuration and its autotuner (not part of the paper).     */
 /* ---------------------------------------------------------------------- */
-/* Configurations of the per-pair merge (workgroup threads x items per
- * thread): 0 = 512 threads, large tiles (about 70 KB of LDS per tile);
- * 1 = 256 threads, same items per thread; 2 = 256 threads, half the items. */
-#define IM_LEAF_CONFIGS 3
+/* Configurations of the per-pair merge: workgroup threads x items per
+ * thread, and pipeline depth (tiles a workgroup reads ahead of the oldest
+ * one it has not stored; a pair may span depth x resident-workgroups tiles,
+ * so depth 3 needs fewer division levels and depth 2 keeps one register set):
+ *   0 = 512 threads, large tiles (about 70 KB of LDS), depth 3;
+ *   1 = 512 threads, large tiles, depth 2;
+ *   2 = 256 threads, same items per thread, depth 2;
+ *   3 = 256 threads, half the items per thread, depth 3. */
+#define IM_LEAF_CONFIGS 4
 
 /* Force a configuration for the calling process (0..IM_LEAF_CONFIGS-1), or
  * -1 to return to automatic choice (tuned table, else configuration 0). */

@@ -34,7 +34,7 @@ _lib = None
 
 MLP_HIDDEN = 32
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
-LEAF_CONFIGS = 3
+LEAF_CONFIGS = 4
 
 # im_dtype codes of the C ABI
 _DT = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3}

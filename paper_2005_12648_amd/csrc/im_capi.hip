@@ -150,22 +150,33 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     if (ds->grid[cfg][ki][vi] == 0) ds->grid[cfg][ki][vi] = leaf_grid(ek, ev, cfg);
     int G = ds->grid[cfg][ki][vi];
     if (G <= 0) return false;
-    int th, ipt;
+    // test hook: a smaller persistent grid (more slots per workgroup, so the
+    // read-ahead and the waits of the leaf merge are exercised on small inputs)
+    if (const char *g_env = std::getenv("IM_LEAF_GRID")) {
+        long v = std::strtol(g_env, nullptr, 10);
+        if (v >= 1 && v < G) G = (int)v;
+    }
+    int th, ipt, depth;
     size_t lds;
-    leaf_geometry(ek, ev, cfg, &th, &ipt, &lds);
+    leaf_geometry(ek, ev, cfg, &th, &ipt, &depth, &lds);
     pl->cfg = cfg;
-    const char *cap_env = std::getenv("IM_LEAF_TILES");   // test hook: tiles per leaf cap
-    int64_t tiles_per_leaf = G;
-    if (cap_env) {
+    // Every workgroup of the leaf merge reads `depth` tiles ahead of its
+    // oldest unstored one (im_leaf.hip), so readers less than depth*G slots
+    // ahead never block: a leaf may have depth*G tiles.  (Measured: the full
+    // capacity beats one with a round of slack on balanced and skewed
+    // merges.)  IM_LEAF_TILES (tests, tuning) sets any capacity from 1 to
+    // depth*G tiles.
+    int64_t tiles_per_leaf = (int64_t)depth * G;
+    if (const char *cap_env = std::getenv("IM_LEAF_TILES")) {
         long v = std::strtol(cap_env, nullptr, 10);
-        if (v >= 1 && v < tiles_per_leaf) tiles_per_leaf = v;
+        if (v >= 1 && v <= (int64_t)depth * G) tiles_per_leaf = v;
     }
     pl->n_inst = n_inst;
     pl->total = total;
     pl->tile = (int64_t)th * ipt;
     pl->leaf_cap = tiles_per_leaf * pl->tile;
-    // A leaf may be larger than the grid when its smaller part keeps every
-    // element within G-2 tiles of its source (im_leaf.hip, slot order).
+    // A leaf may be larger still when its smaller part keeps every element
+    // within tiles_per_leaf-2 tiles of its source (im_leaf.hip, slot order).
     pl->leaf_span = (tiles_per_leaf > 2 ? tiles_per_leaf - 2 : 0) * pl->tile;
     pl->grid_leaf = G;
     if (max_inst <= 0 || max_inst > total) max_inst = total;
@@ -657,9 +668,9 @@ int batched_inplace_merge_graph(im_graph **out, void *data, const int64_t *d_off
     }
     Work w;
     carve(pl, 0, g->ws, &w);
-    int th, ipt;
+    int th, ipt, depth;
     size_t lds;
-    leaf_geometry(ek, 0, pl.cfg, &th, &ipt, &lds);
+    leaf_geometry(ek, 0, pl.cfg, &th, &ipt, &depth, &lds);
     const void *leaf_fn = leaf_kernel_ptr(dtype, 0, pl.cfg);
     hipError_t e = leaf_fn ? hipFuncSetAttribute(leaf_fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds)

@@ -103,7 +103,7 @@ struct Plan {
     int32_t cfg;            // leaf-merge configuration (tile size per workgroup)
 };
 
-constexpr int kLeafCfgs = 3;   // leaf-merge tile configurations (im_leaf.hip)
+constexpr int kLeafCfgs = 4;   // leaf-merge tile configurations (im_leaf.hip)
 
 // Workspace carve-up (device pointers).
 struct Work {
@@ -136,8 +136,11 @@ hipError_t launch_leafmerge(int key, int esize_v, void *keys, void *vals, const 
                             const Work &w, hipStream_t s);
 hipError_t launch_tiledeps(const Plan &pl, const Work &w, hipStream_t s);
 hipError_t launch_fill32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
-// Tile geometry of the leaf merge for a (key size, payload size, config).
-void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, size_t *lds_bytes);
+// Tile geometry of the leaf merge for a (key size, payload size, config):
+// threads per workgroup, items per thread, pipeline depth (tiles read ahead
+// of the oldest unstored one: a leaf may have depth * grid tiles), LDS bytes.
+void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, int *depth,
+                   size_t *lds_bytes);
 int leaf_grid(int esize_k, int esize_v, int cfg);   // persistent grid (resident workgroups)
 const void *leaf_kernel_ptr(int key, int esize_v, int cfg);
 

@@ -20,14 +20,18 @@
 // The grid is persistent and co-resident (cooperative launch); processing
 // slot s is handled by workgroup s mod G in increasing s.  Within a leaf the
 // slots visit the tiles in increasing order when every A element moves right
-// by at most (G-2) tiles (the leaf's B-part is within the leaf span, or the
-// whole leaf has at most G tiles), else in decreasing order (then its A-part
-// is within the span and every B element moves left by at most (G-2) tiles).
-// Either way every tile that reads a window lies less than G slots after
-// it, so the workgroup holding it has finished all its earlier slots: the
-// smallest unfinished slot always makes progress and the waits cannot
-// deadlock.  The wait is bounded: on expiry the workgroup raises an error
-// bit and skips its store.
+// by at most the leaf span (the leaf's B-part is within the span, or the
+// whole leaf is within the leaf capacity), else in decreasing order (then
+// its A-part is within the span and every B element moves left by at most
+// the span).  The planner keeps every reader less than 3G slots after the
+// tile it reads.  Deadlock
+// freedom: let s be the smallest slot not yet stored.  Every workgroup has
+// stored all its slots below s, so it sits at its first slot c >= s
+// (c < s+G); before its first wait it has read c, c+G and c+2G (one tile in
+// registers, one merged into a second register set, one staged in LDS).  The
+// slots [s, s+3G) are therefore all read without any wait, the readers of
+// s's window are among them, and s is stored.  The wait is bounded: on
+// expiry the workgroup raises an error bit and skips its store.
 #include <type_traits>
 #include "im_common.h"
 
@@ -40,52 +44,75 @@ constexpr unsigned kSpinLimit = 1u << 26;
 template <int T>
 struct LdsPad { static constexpr int elems = T + 2; };   // + look-ahead slack
 
-// Geometry of one tile: its leaf, output window [d0, d0+n) inside the leaf,
-// and where its A-slice (na elements) and B-slice (n - na) start.
+// Geometry of one tile: output window [out0, out0+n), A-slice (na elements
+// from a0) and B-slice (n - na elements from b0), all as element indices of
+// the whole buffer; its leaf's tile range and the range of tiles that read
+// its window.
 struct TileGeo {
-    int64_t base, d0, tbase;
-    int n, na, a_off, b_off;
-    int32_t leaf, ntiles, local, wlo, whi;
+    int64_t out0, a0, b0, tbase;
+    int n, na;
+    int32_t ntiles, local, wlo, whi;
 };
+
+// The slot index is the same in every lane: the geometry is read once per
+// wave and kept in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int32_t uniform32(int32_t v) {
+    return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
 
 // Geometry of the tile processed in slot s (the slot order reverses the
 // tiles of a dir-1 leaf).
 __device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t s, int T) {
     TileGeo g;
-    const int32_t l = w.tile_leaf[s];
+    s = uniform64(s);
+    const int32_t l = uniform32(w.tile_leaf[s]);
     const Leaf lf = w.leaves[l];
-    const int64_t sl = s - w.tile_start[l];
-    const int64_t local = lf.dir ? (int64_t)lf.ntiles - 1 - sl : sl;
-    const int64_t t = w.tile_start[l] + local;
-    const int64_t S = lf.la + lf.lb;
+    const int64_t base = uniform64(lf.base), la = uniform64(lf.la), lb = uniform64(lf.lb);
+    const int32_t ntiles = uniform32(lf.ntiles), dir = uniform32(lf.dir);
+    const int64_t tstart = uniform64(w.tile_start[l]);
+    const int64_t sl = s - tstart;
+    const int64_t local = dir ? (int64_t)ntiles - 1 - sl : sl;
+    const int64_t t = tstart + local;
+    const int64_t S = la + lb;
     const int64_t d0 = local * (int64_t)T;
     const int64_t d1 = d0 + T < S ? d0 + T : S;
     const int n = (int)(d1 - d0);
-    const int64_t ia0 = w.tile_rank[t];
-    const int64_t ia1 = (local + 1 < lf.ntiles) ? w.tile_rank[t + 1] : lf.la;
+    const int64_t ia0 = uniform64(w.tile_rank[t]);
+    const int64_t ia1 = (local + 1 < ntiles) ? uniform64(w.tile_rank[t + 1]) : la;
     // For ascending runs na = ia1 - ia0 already lies in this interval; the
     // clamp only keeps every access inside the leaf when a caller passes
     // unsorted runs (then the result is an unspecified permutation).
     int64_t na64 = ia1 - ia0;
-    const int64_t na_lo = (d1 - lf.lb - ia0) > 0 ? (d1 - lf.lb - ia0) : 0;
-    const int64_t na_hi = (lf.la - ia0) < (int64_t)n ? (lf.la - ia0) : (int64_t)n;
+    const int64_t na_lo = (d1 - lb - ia0) > 0 ? (d1 - lb - ia0) : 0;
+    const int64_t na_hi = (la - ia0) < (int64_t)n ? (la - ia0) : (int64_t)n;
     if (na64 < na_lo) na64 = na_lo;
     if (na64 > na_hi) na64 = na_hi;
-    g.base = lf.base;
-    g.d0 = d0;
+    g.out0 = base + d0;
     g.n = n;
     g.na = (int)na64;
-    // Offsets relative to the leaf start (a leaf is far below 2^31
-    // elements): every address is a uniform base plus one 32-bit offset.
-    g.a_off = (int)ia0;                                   // A-slice start
-    g.b_off = (int)(lf.la + (d0 - ia0)) - g.na;           // B-slice start, minus na
-    g.leaf = l;
-    g.ntiles = lf.ntiles;
-    g.tbase = w.tile_start[l];
+    g.a0 = base + ia0;                     // A elements before the window: ia0
+    g.b0 = base + la + (d0 - ia0);         // B elements before the window: d0 - ia0
+    g.ntiles = ntiles;
+    g.tbase = tstart;
     g.local = (int32_t)local;
-    g.wlo = w.tile_dep[2 * t];
-    g.whi = w.tile_dep[2 * t + 1];
+    g.wlo = uniform32(w.tile_dep[2 * t]);
+    g.whi = uniform32(w.tile_dep[2 * t + 1]);
     return g;
+}
+
+// Raw buffer resources (base, byte size): a buffer access takes a 32-bit
+// per-lane offset next to a wave-uniform descriptor, so the tile loops need
+// no 64-bit address per element.  Word 3 selects a raw 32-bit buffer
+// without swizzling on CDNA.
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kBufWord3);
 }
 
 // Copy a tile's A-slice and B-slice (one contiguous logical range [0, n))
@@ -93,71 +120,72 @@ __device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t s, int T) {
 // load of the tile in flight at once.  The copy runs over 32-bit words: lane
 // slot j = tid + u*THREADS moves word j of the LDS image, i.e. word j % D of
 // element j / D (D words per element); a wave's 64 slots are contiguous in
-// LDS, as the DMA requires (destination = wave base + 4 * lane).  The caller
-// waits for completion (vmcnt) before reading.
+// LDS, as the DMA requires (destination = wave base + 4 * lane).  Words below
+// na*D come from the A-slice, the rest from the B-slice.  The caller waits
+// for completion (vmcnt) before reading.  (Measured: the buffer-descriptor
+// form of the same DMA, buffer_load_dword ... lds, is about 6% slower here.)
 template <typename E, int THREADS, int IPT>
 __device__ __forceinline__ void stage_tile_dma(const E *__restrict__ base_ptr, const TileGeo &g,
                                                E *__restrict__ s) {
     constexpr int D = (int)(sizeof(E) / 4);
-    const uint32_t *L = reinterpret_cast<const uint32_t *>(base_ptr + g.base);
+    const uint32_t *A = reinterpret_cast<const uint32_t *>(base_ptr + g.a0);
+    const uint32_t *B = reinterpret_cast<const uint32_t *>(base_ptr + g.b0);
     uint32_t *S = reinterpret_cast<uint32_t *>(s);
     int xb = threadIdx.x;
     asm volatile("" : "+v"(xb));
     const int wbase = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
-    const int nw = g.n * D;
+    const int naw = g.na * D, nw = g.n * D;
 #pragma unroll
     for (int u = 0; u < IPT * D; ++u) {
         const int j = xb + u * THREADS;
         if (j < nw) {
-            const int x = j / D;                      // D is 1 or 2: a shift
-            const int src = x < g.na ? g.a_off + x : g.b_off + x;
-            __builtin_amdgcn_global_load_lds(L + (int64_t)src * D + (j - x * D),
-                                             S + wbase + u * THREADS, 4, 0, 0);
+            const uint32_t *src = j < naw ? A + j : B + (j - naw);
+            __builtin_amdgcn_global_load_lds(src, S + wbase + u * THREADS, 4, 0, 0);
         }
+    }
+}
+
+// Store one element through a buffer descriptor (byte offset).
+template <typename E>
+__device__ __forceinline__ void buf_store(E v, __amdgpu_buffer_rsrc_t r, int off) {
+    if constexpr (sizeof(E) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+    } else {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
     }
 }
 
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Pipeline per workgroup (slots t, t+G, t+2G, ...):
-//   merge(t) from LDS into registers -> transpose the outputs through LDS
-//   (blocked -> striped) -> stage(t+G) into LDS and publish its flag ->
-//   wait for the readers of t's window -> coalesced store of t from
-//   registers.
-// The next tile is staged and flagged before this tile waits, so a tile's
-// flag only needs the workgroup's slot two rounds back to be finished: the
-// readers (at most G-1 slots ahead, see the leaf span) are always reachable
-// with a full round of slack, and waits rarely stall.
+// Pieces of the leaf-merge pipeline for one workgroup.
 template <typename K, typename V, int THREADS, int IPT>
-__global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
-                                                          Plan pl, Work w) {
-    constexpr int T = THREADS * IPT;
-    constexpr bool HAS_V = !std::is_same<V, NoValL>::value;
-    constexpr int PE = LdsPad<T>::elems;
-    extern __shared__ __align__(16) unsigned char smem[];
-    K *sk = reinterpret_cast<K *>(smem);
-    V *sv = reinterpret_cast<V *>(smem + (size_t)PE * sizeof(K));
+struct LeafOps {
+    static constexpr int T = THREADS * IPT;
+    static constexpr bool HAS_V = !std::is_same<V, NoValL>::value;
+    static constexpr int PE = LdsPad<T>::elems;
+    static constexpr int VN = HAS_V ? IPT : 1;
 
-    const int tid = threadIdx.x;
-    int64_t ntiles = (int64_t)w.ctr->tiles;
-    if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
-    int64_t t = blockIdx.x;
-    if (t >= ntiles) return;
+    // Load the tile's slices into LDS and publish "inputs read".
+    static __device__ __forceinline__ void stage(const K *keys, const V *vals, const TileGeo &g,
+                                                 K *sk, V *sv, const Plan &pl, const Work &w) {
+        stage_tile_dma<K, THREADS, IPT>(keys, g, sk);
+        if constexpr (HAS_V) stage_tile_dma<V, THREADS, IPT>(vals, g, sv);
+        wait_dma();
+        __syncthreads();
+        if (g.ntiles > 1 && threadIdx.x == 0)
+            __hip_atomic_store(&w.tile_flag[g.tbase + g.local], pl.epoch, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
 
-    TileGeo g = tile_geo(w, t, T);
-    stage_tile_dma<K, THREADS, IPT>(keys, g, sk);
-    if constexpr (HAS_V) stage_tile_dma<V, THREADS, IPT>(vals, g, sv);
-    wait_dma();
-    __syncthreads();
-    if (g.ntiles > 1 && tid == 0)            // this tile's inputs are read
-        __hip_atomic_store(&w.tile_flag[g.tbase + g.local], pl.epoch, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-
-    for (;;) {
-        // 1. per-thread merge path inside LDS (stable: ties take A)
+    // Merge the tile held in LDS into registers (stable: ties take A), then
+    // transpose through LDS so that thread p holds outputs p + u*THREADS
+    // (coalesced stores).  Leaves the LDS free.
+    template <bool MATERIALISE>
+    static __device__ __forceinline__ void merge(const TileGeo &g, K *sk, V *sv, K (&out)[IPT],
+                                                 V (&vout)[VN]) {
+        const int tid = threadIdx.x;
         const int n = g.n, na = g.na, nb = g.n - g.na;
-        K out[IPT];
-        V vout[HAS_V ? IPT : 1];
         {
             int d = tid * IPT;
             if (d > n) d = n;
@@ -172,109 +200,193 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
             // sk has PE > n entries, so the look-ahead reads stay inside LDS.
             K a = sk[ia];
             K b = sk[na + ib];
+            // branch-free steps (selects only): no per-step exec masks
 #pragma unroll
             for (int e = 0; e < IPT; ++e) {
-                bool ta = (ib >= nb) || (ia < na && a <= b);
-                out[e] = ta ? a : b;
-                int src = ta ? ia : na + ib;
+                const bool ta = (ib >= nb) || (ia < na && a <= b);
+                K o = ta ? a : b;
+                // With two register sets live (depth 3), materialise the
+                // output now: otherwise the select is sunk to its use and
+                // both candidates plus the mask stay live, which spills.
+                if constexpr (MATERIALISE) asm volatile("" : "+v"(o));
+                out[e] = o;
+                const int src = ta ? ia : na + ib;
                 if constexpr (HAS_V) vout[e] = sv[src > PE - 1 ? PE - 1 : src];
-                int nx = src + 1;
-                if (nx > PE - 1) nx = PE - 1;
-                K v = sk[nx];
-                if (ta) { ++ia; a = v; } else { ++ib; b = v; }
+                const int nx = src + 1 > PE - 1 ? PE - 1 : src + 1;
+                const K v = sk[nx];
+                ia += ta ? 1 : 0;
+                ib += ta ? 0 : 1;
+                a = ta ? v : a;
+                b = ta ? b : v;
             }
         }
         __syncthreads();                     // LDS inputs of this tile are dead
-
-        // 2. blocked -> striped through LDS: thread p holds outputs
-        // p*IPT + e; after the round trip it holds tid + u*THREADS, so the
-        // final stores are coalesced.  IPT is odd: the blocked writes (stride
-        // IPT words) hit distinct banks.
-        {
-            const int x0 = tid * IPT;
+        // blocked -> striped: IPT is odd, so the blocked writes (stride IPT
+        // words) hit distinct banks.
+        const int x0 = tid * IPT;
 #pragma unroll
-            for (int e = 0; e < IPT; ++e) {
-                if (x0 + e < n) {
-                    sk[x0 + e] = out[e];
-                    if constexpr (HAS_V) sv[x0 + e] = vout[e];
-                }
+        for (int e = 0; e < IPT; ++e) {
+            if (x0 + e < n) {
+                sk[x0 + e] = out[e];
+                if constexpr (HAS_V) sv[x0 + e] = vout[e];
             }
-            __syncthreads();
-            int xb = tid;
-            asm volatile("" : "+v"(xb));
-#pragma unroll
-            for (int u = 0; u < IPT; ++u) {
-                const int x = xb + u * THREADS;
-                if (x < n) {
-                    out[u] = sk[x];
-                    if constexpr (HAS_V) vout[u] = sv[x];
-                }
-            }
-            __syncthreads();
-        }
-
-        // 3. stage the next tile of this workgroup and publish its flag
-        const int64_t tn = t + gridDim.x;
-        const bool has_next = tn < ntiles;
-        TileGeo gn = g;
-        if (has_next) {
-            gn = tile_geo(w, tn, T);
-            stage_tile_dma<K, THREADS, IPT>(keys, gn, sk);
-            if constexpr (HAS_V) stage_tile_dma<V, THREADS, IPT>(vals, gn, sv);
-            wait_dma();
         }
         __syncthreads();
-        if (has_next && gn.ntiles > 1 && tid == 0)
-            __hip_atomic_store(&w.tile_flag[gn.tbase + gn.local], pl.epoch, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-
-        // 4. wait until every tile that reads this window has its inputs in
-        // LDS.  Flags are touched only with relaxed device-scope atomics: the
-        // readers' loads have returned before they publish, and an
-        // acquire/release fence at device scope would write back or
-        // invalidate this XCD's whole L2 on every poll.
-        int ok = 1;
-        if (g.ntiles > 1) {
-            int bad = 0;
-            for (int q = g.wlo + tid; q <= g.whi && !bad; q += THREADS) {
-                if (q == g.local) continue;
-                const unsigned *f = &w.tile_flag[g.tbase + q];
-                unsigned spins = 0;
-                while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-                       pl.epoch) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > kSpinLimit) { bad = 1; break; }
-                }
-            }
-            bad = __syncthreads_or(bad);
-            if (bad) {
-                if (tid == 0) atomicOr(&w.ctr->error, kErrBarrierSpin);
-                ok = 0;
+        int xb = tid;
+        asm volatile("" : "+v"(xb));
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const int x = xb + u * THREADS;
+            if (x < n) {
+                out[u] = sk[x];
+                if constexpr (HAS_V) vout[u] = sv[x];
             }
         }
+        __syncthreads();
+    }
 
-        // 5. coalesced store of this tile's window from registers
-        if (ok) {
-            int xb = tid;
-            asm volatile("" : "+v"(xb));
-            K *O = keys + g.base + g.d0;
+    // Wait until every tile that reads this window has its inputs on chip.
+    // Flags are touched only with relaxed device-scope atomics: the readers'
+    // loads have returned before they publish, and an acquire/release fence
+    // at device scope would write back or invalidate this XCD's whole L2 on
+    // every poll.  Returns false if the bounded wait expired.
+    static __device__ __forceinline__ bool wait_readers(const TileGeo &g, const Plan &pl,
+                                                        const Work &w) {
+        if (g.ntiles <= 1) return true;
+        int bad = 0;
+        for (int q = g.wlo + (int)threadIdx.x; q <= g.whi && !bad; q += THREADS) {
+            if (q == g.local) continue;
+            const unsigned *f = &w.tile_flag[g.tbase + q];
+            unsigned spins = 0;
+            while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pl.epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) { bad = 1; break; }
+            }
+        }
+        bad = __syncthreads_or(bad);
+        if (bad && threadIdx.x == 0) atomicOr(&w.ctr->error, kErrBarrierSpin);
+        return !bad;
+    }
+
+    // Coalesced store of the window from registers.
+    static __device__ __forceinline__ void store(K *keys, V *vals, const TileGeo &g,
+                                                 const K (&out)[IPT], const V (&vout)[VN]) {
+        const int n = g.n;
+        int xb = threadIdx.x;
+        asm volatile("" : "+v"(xb));
+        const __amdgpu_buffer_rsrc_t ro = buf_rsrc(keys + g.out0, (int64_t)n * sizeof(K));
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const int x = xb + u * THREADS;
+            if (x < n) buf_store<K>(out[u], ro, x * (int)sizeof(K));
+        }
+        if constexpr (HAS_V) {
+            const __amdgpu_buffer_rsrc_t rv =
+                buf_rsrc(vals + g.out0, (int64_t)n * sizeof(V));
 #pragma unroll
             for (int u = 0; u < IPT; ++u) {
                 const int x = xb + u * THREADS;
-                if (x < n) O[x] = out[u];
-            }
-            if constexpr (HAS_V) {
-                V *OV = vals + g.base + g.d0;
-#pragma unroll
-                for (int u = 0; u < IPT; ++u) {
-                    const int x = xb + u * THREADS;
-                    if (x < n) OV[x] = vout[u];
-                }
+                if (x < n) buf_store<V>(vout[u], rv, x * (int)sizeof(V));
             }
         }
-        if (!has_next) break;
-        t = tn;
-        g = gn;
+    }
+};
+
+// Pipeline state of one workgroup: tile t (merged, in registers `cur`),
+// tile t+G (staged in LDS), and their geometry.
+struct LeafPipe {
+    int64_t t, ntiles;
+    bool has1;            // tile t+G exists (and is staged)
+    TileGeo g, g1;
+};
+
+// One step: merge t+G from LDS into `nxt`, stage t+2G into LDS, wait for
+// the readers of t's window, store t from `cur`, advance.  Returns false
+// after the workgroup's last tile.
+template <typename K, typename V, int THREADS, int IPT>
+__device__ __forceinline__ bool leaf_step(K *keys, V *vals, K *sk, V *sv, const Plan &pl,
+                                          const Work &w, LeafPipe &p,
+                                          K (&cur)[IPT], V (&vcur)[LeafOps<K, V, THREADS, IPT>::VN],
+                                          K (&nxt)[IPT], V (&vnxt)[LeafOps<K, V, THREADS, IPT>::VN]) {
+    using Ops = LeafOps<K, V, THREADS, IPT>;
+    const int64_t G = gridDim.x;
+    if (p.has1) Ops::template merge<true>(p.g1, sk, sv, nxt, vnxt);
+    const int64_t t2 = p.t + 2 * G;
+    const bool has2 = p.has1 && t2 < p.ntiles;
+    TileGeo g2 = p.g1;
+    if (has2) {
+        g2 = tile_geo(w, t2, Ops::T);
+        Ops::stage(keys, vals, g2, sk, sv, pl, w);
+    }
+    if (Ops::wait_readers(p.g, pl, w)) Ops::store(keys, vals, p.g, cur, vcur);
+    if (!p.has1) return false;
+    p.t += G;
+    p.g = p.g1;
+    p.has1 = has2;
+    p.g1 = g2;
+    return true;
+}
+
+// Pipeline per workgroup (slots t, t+G, t+2G, ...).
+//   DEPTH 2: merge t from LDS into registers, stage t+G into LDS and flag it,
+//            wait for the readers of t's window, store t.  Two tiles are read
+//            at or beyond the oldest unstored slot: readers may be up to
+//            2G-1 slots ahead.
+//   DEPTH 3: tile t waits and is stored only after t+G has been merged into
+//            a second register set and t+2G has been staged into LDS and
+//            flagged: readers may be up to 3G-1 slots ahead (larger leaves,
+//            fewer division levels), at the price of a second register set.
+template <typename K, typename V, int THREADS, int IPT, int DEPTH>
+__global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
+                                                          Plan pl, Work w) {
+    using Ops = LeafOps<K, V, THREADS, IPT>;
+    static_assert(DEPTH == 2 || DEPTH == 3, "pipeline depth");
+    extern __shared__ __align__(16) unsigned char smem[];
+    K *sk = reinterpret_cast<K *>(smem);
+    V *sv = reinterpret_cast<V *>(smem + (size_t)Ops::PE * sizeof(K));
+
+    LeafPipe p;
+    p.ntiles = (int64_t)w.ctr->tiles;
+    if (p.ntiles > pl.cap_tiles) p.ntiles = pl.cap_tiles;
+    p.t = blockIdx.x;
+    if (p.t >= p.ntiles) return;
+    const int64_t G = gridDim.x;
+
+    K ra[IPT];
+    V va[Ops::VN];
+    p.g = tile_geo(w, p.t, Ops::T);
+    Ops::stage(keys, vals, p.g, sk, sv, pl, w);
+    if constexpr (DEPTH == 2) {
+        for (;;) {
+            Ops::template merge<false>(p.g, sk, sv, ra, va);
+            const int64_t tn = p.t + G;
+            const bool has_next = tn < p.ntiles;
+            TileGeo gn = p.g;
+            if (has_next) {
+                gn = tile_geo(w, tn, Ops::T);
+                Ops::stage(keys, vals, gn, sk, sv, pl, w);
+            }
+            if (Ops::wait_readers(p.g, pl, w)) Ops::store(keys, vals, p.g, ra, va);
+            if (!has_next) break;
+            p.t = tn;
+            p.g = gn;
+        }
+    } else {
+        K rb[IPT];
+        V vb[Ops::VN];
+        // prologue: t into registers, t+G into LDS
+        Ops::template merge<true>(p.g, sk, sv, ra, va);
+        p.has1 = p.t + G < p.ntiles;
+        p.g1 = p.g;
+        if (p.has1) {
+            p.g1 = tile_geo(w, p.t + G, Ops::T);
+            Ops::stage(keys, vals, p.g1, sk, sv, pl, w);
+        }
+        // the two register sets alternate roles
+        for (;;) {
+            if (!leaf_step<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, ra, va, rb, vb)) break;
+            if (!leaf_step<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, rb, vb, ra, va)) break;
+        }
     }
 }
 
@@ -409,36 +521,42 @@ hipError_t launch_plan(const Plan &pl, const Work &w, hipStream_t s) {
 }
 
 // ---- geometry and dispatch ----------------------------------------------
-// (key bytes, payload bytes, config) -> (threads, items per thread).  Items
-// per thread are odd, so the blocked LDS accesses are bank-conflict free.
-//   config 0: 8 waves per tile, about 70 KB of LDS (two workgroups fill a CU)
-//   config 1: 4 waves per tile, same items per thread (half the tile, four
-//             workgroups per CU): finer granularity for many small instances
-//   config 2: 4 waves per tile, half the items per thread (quarter tile)
-// The tiles resident on the chip bound how far a leaf may move elements, so
-// the smaller tiles trade shorter pipelines for more division levels on
-// large merges; the autotuner measures the trade per workload class.
+// (key bytes, payload bytes, config) -> (threads, items per thread, depth).
+// Items per thread are odd, so the blocked LDS accesses are bank-conflict
+// free.
+//   config 0: 8 waves per tile, about 70 KB of LDS (two workgroups fill a
+//             CU), pipeline depth 3: the largest leaves
+//   config 1: as 0 with depth 2 (one register set, smaller leaves)
+//   config 2: 4 waves per tile, same items per thread (half the tile, four
+//             workgroups per CU), depth 2: finer grain for many instances
+//   config 3: 4 waves per tile, half the items per thread, depth 3
+// The tiles the chip holds on chip bound how far a leaf may move elements,
+// so the variants trade pipeline overlap against division levels; the
+// autotuner measures the trade per workload class.
 static int ipt_big(int eb) { return eb <= 4 ? 35 : (eb <= 8 ? 17 : (eb <= 12 ? 11 : 9)); }
 static int ipt_small(int eb) { return eb <= 4 ? 17 : (eb <= 8 ? 9 : 5); }
 
-static void geom(int ek, int ev, int cfg, int *th, int *ipt) {
+static void geom(int ek, int ev, int cfg, int *th, int *ipt, int *depth) {
     const int eb = ek + ev;
-    *th = cfg == 0 ? 512 : 256;
-    *ipt = cfg == 2 ? ipt_small(eb) : ipt_big(eb);
+    *th = cfg <= 1 ? 512 : 256;
+    *ipt = cfg == 3 ? ipt_small(eb) : ipt_big(eb);
+    *depth = (cfg == 0 || cfg == 3) ? 3 : 2;
 }
 
-void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, size_t *lds_bytes) {
-    geom(esize_k, esize_v, cfg, threads, ipt);
+void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, int *depth,
+                   size_t *lds_bytes) {
+    geom(esize_k, esize_v, cfg, threads, ipt, depth);
     int T = *threads * *ipt;
     size_t pe = (size_t)(T + 2);
     *lds_bytes = pe * esize_k + pe * esize_v;
 }
 
-// One line per (key, payload): the three configurations' (threads, items).
+// One line per (key, payload): the configurations' (threads, items, depth).
 #define IM_LEAF_KV(X, K, V, BIG, SMALL) \
-    X(K, V, 0, 512, BIG)                \
-    X(K, V, 1, 256, BIG)                \
-    X(K, V, 2, 256, SMALL)
+    X(K, V, 0, 512, BIG, 3)             \
+    X(K, V, 1, 512, BIG, 2)             \
+    X(K, V, 2, 256, BIG, 2)             \
+    X(K, V, 3, 256, SMALL, 3)
 
 #define IM_LEAF_CASES(X)                        \
     IM_LEAF_KV(X, int32_t, NoValL, 35, 17)      \
@@ -463,18 +581,18 @@ template <typename V> struct ValSize { static constexpr int v = sizeof(V); };
 template <> struct ValSize<NoValL> { static constexpr int v = 0; };
 
 const void *leaf_kernel_ptr(int key, int esize_v, int cfg) {
-#define X(K, V, C, TH, IPT)                                                      \
+#define X(K, V, C, TH, IPT, DEPTH)                                               \
     if (KeyOf<K>::code == key && ValSize<V>::v == esize_v && C == cfg)         \
-        return (const void *)&k_leafmerge<K, V, TH, IPT>;
+        return (const void *)&k_leafmerge<K, V, TH, IPT, DEPTH>;
     IM_LEAF_CASES(X)
 #undef X
     return nullptr;
 }
 
 int leaf_grid(int esize_k, int esize_v, int cfg) {
-    int th, ipt;
+    int th, ipt, depth;
     size_t lds;
-    leaf_geometry(esize_k, esize_v, cfg, &th, &ipt, &lds);
+    leaf_geometry(esize_k, esize_v, cfg, &th, &ipt, &depth, &lds);
     int key = esize_k == 4 ? kI32 : kI64;
     const void *fn = leaf_kernel_ptr(key, esize_v, cfg);
     if (!fn) return 0;
@@ -491,10 +609,10 @@ int leaf_grid(int esize_k, int esize_v, int cfg) {
 
 hipError_t launch_leafmerge(int key, int esize_v, void *keys, void *vals, const Plan &pl,
                             const Work &w, hipStream_t s) {
-    int th, ipt;
+    int th, ipt, depth;
     size_t lds;
     int esize_k = (key == kI32 || key == kU32) ? 4 : 8;
-    leaf_geometry(esize_k, esize_v, pl.cfg, &th, &ipt, &lds);
+    leaf_geometry(esize_k, esize_v, pl.cfg, &th, &ipt, &depth, &lds);
     const void *fn = leaf_kernel_ptr(key, esize_v, pl.cfg);
     if (!fn) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

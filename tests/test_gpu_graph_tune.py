@@ -1,8 +1,8 @@
 """Leaf-merge configurations, the captured (HIP graph) batched merge and the
 autotuner: every result is compared with the CPU oracle element by element.
 
-* each of the three leaf configurations (8 or 4 waves per tile, large or
-  half-size tiles) is forced in turn on single pairs (several tiles, ragged
+* each of the four leaf configurations (8 or 4 waves per tile, large or
+  half-size tiles, pipeline depth 2 or 3) is forced in turn on single pairs (several tiles, ragged
   tails, division levels via IM_LEAF_TILES), key+payload pairs and batches;
 * a graph is recorded once and replayed several times on new contents of the
   same buffers, with eager merges and other device work between the replays;
@@ -64,7 +64,7 @@ def check_batch(got, data, off, label):
 
 
 # ------------------------------------------------------ forced configurations
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 @pytest.mark.parametrize("tiles", [None, 3, 1])
 @pytest.mark.parametrize("dt", [np.int32, np.uint64])
 def test_config_pairs(dev, leaf_cfg, leaf_tiles, cfg, tiles, dt):
@@ -83,7 +83,7 @@ def test_config_pairs(dev, leaf_cfg, leaf_tiles, cfg, tiles, dt):
         assert bad.size == 0, "%d mismatches, first at %d" % (bad.size, bad[0])
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 @pytest.mark.parametrize("vdt", [np.uint32, np.uint64])
 def test_config_kv(dev, leaf_cfg, leaf_tiles, cfg, vdt):
     leaf_cfg(cfg)
@@ -99,7 +99,7 @@ def test_config_kv(dev, leaf_cfg, leaf_tiles, cfg, vdt):
     assert np.array_equal(h(tv), wv)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 def test_config_batched(dev, leaf_cfg, cfg):
     leaf_cfg(cfg)
     data, off = gen.batch(200, 51, lo_exp=0.0, hi_exp=16.0)

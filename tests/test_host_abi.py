@@ -73,7 +73,7 @@ def test_validation_codes_without_device_work():
     assert lib.im_graph_launch(None, None) == -1
     assert lib.im_graph_cooperative(None) == 0
     assert lib.im_graph_destroy(None) == 0
-    assert lib.inplace_merge_set_config(3) == -1
+    assert lib.inplace_merge_set_config(4) == -1
     assert lib.inplace_merge_set_config(-2) == -1
     assert lib.inplace_merge_set_config(-1) == 0
     assert lib.inplace_merge_autotune(fake, fake, 4, 100, 0, 9, -1, 3, None, None, None) == -2
