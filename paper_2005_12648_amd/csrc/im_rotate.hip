@@ -21,162 +21,204 @@
 
 namespace imerge {
 
-constexpr int kRotThreads = 256;
-constexpr int kRotPer = (int)(kRotChunk / kRotThreads);   // pairs per thread
+// Threads per workgroup by bytes moved per element (key + payload): each
+// thread holds kRotChunk / threads pairs, twice (software pipeline), so wider
+// elements take more threads to keep the registers per thread bounded.
+template <int BYTES>
+struct RotGeom {
+    static constexpr int threads = BYTES <= 4 ? 256 : (BYTES <= 8 ? 512 : 1024);
+    static constexpr int per = (int)(kRotChunk / threads);   // pairs per thread
+};
 
 struct NoVal {};
 
-// 16-byte vectors with only element alignment: gfx950 runs global memory in
-// unaligned-access mode, so each becomes one dwordx4 access (used by the
-// reversals, where they measured faster than element accesses).
-template <typename E>
-struct __attribute__((aligned(sizeof(E)))) Vec {
-    static constexpr int N = 16 / (int)sizeof(E);
-    E v[N];
+// One work item is a run of element pairs (X[t], Y[dir*t]) for t in
+// [0, lim): X starts at element xa and runs upwards; Y starts at yb and runs
+// upwards (dir = +1, a block swap) or downwards (dir = -1, the two ends of a
+// reversal).  Every item exchanges its pairs.  Both starts are the same for
+// every lane, so only a 32-bit offset varies per lane.
+struct PairItem {
+    int64_t xa, yb;
+    int32_t dir, lim;
 };
 
-// Swap pairs [c0, c1) of (p[a + t], p[b + t]), one element per lane and
-// access (64 lanes = one contiguous 256-byte run per wave and region).
-// Measured on MI355X, this beats 16-byte vectors here (two independent
-// read streams and two write streams at unrelated alignments).
-template <typename E>
-__device__ __forceinline__ void swap_chunk(E *__restrict__ p, int64_t a, int64_t b, int64_t c0,
-                                           int64_t c1) {
-    E x[kRotPer], y[kRotPer];
-#pragma unroll
-    for (int u = 0; u < kRotPer; ++u) {
-        int64_t t = c0 + threadIdx.x + (int64_t)u * kRotThreads;
-        if (t < c1) { x[u] = p[a + t]; y[u] = p[b + t]; }
-    }
-#pragma unroll
-    for (int u = 0; u < kRotPer; ++u) {
-        int64_t t = c0 + threadIdx.x + (int64_t)u * kRotThreads;
-        if (t < c1) { p[a + t] = y[u]; p[b + t] = x[u]; }
-    }
-}
-
-// Reverse segment [s, s+m): swap pairs (s + t, s + m - 1 - t) for t in
-// [c0, c1).  A vector of pairs t..t+W-1 meets the mirrored vector ending at
-// s+m-1-t, reversed element-wise; vectors that would overlap the mirror
-// (the middle of the segment) or run past c1 fall back to elements.
-template <typename E>
-__device__ __forceinline__ void rev_chunk(E *__restrict__ p, int64_t s, int64_t m, int64_t c0,
-                                          int64_t c1) {
-    using V = Vec<E>;
-    constexpr int W = V::N;
-    constexpr int NV = kRotPer / W;
-    V x[NV], y[NV];
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-        int64_t t = c0 + (int64_t)(threadIdx.x + u * kRotThreads) * W;
-        if (t + W <= c1 && t + W - 1 < m - W - t) {
-            x[u] = *reinterpret_cast<const V *>(p + s + t);
-            y[u] = *reinterpret_cast<const V *>(p + s + m - W - t);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-        int64_t t = c0 + (int64_t)(threadIdx.x + u * kRotThreads) * W;
-        if (t + W <= c1 && t + W - 1 < m - W - t) {
-            V rx, ry;
-#pragma unroll
-            for (int j = 0; j < W; ++j) {
-                rx.v[j] = y[u].v[W - 1 - j];
-                ry.v[j] = x[u].v[W - 1 - j];
-            }
-            *reinterpret_cast<V *>(p + s + t) = rx;
-            *reinterpret_cast<V *>(p + s + m - W - t) = ry;
-        } else {
-            for (int j = 0; j < W; ++j) {
-                const int64_t tt = t + j;
-                if (tt < c1) {
-                    E xa = p[s + tt], yb = p[s + m - 1 - tt];
-                    p[s + tt] = yb;
-                    p[s + m - 1 - tt] = xa;
-                }
-            }
-        }
-    }
-}
-
-template <typename E>
-__device__ __forceinline__ void do_item(E *__restrict__ p, const Rot &R, int64_t local, int phase) {
+// Item `local` of exchange R in this phase; lim = 0 if the phase has no such
+// item.
+//   |X| == |Y|: phase 0 swaps X with Y (one linear-shifting step).
+//   |X| != |Y|: phase 0 reverses X and Y (items of X first), phase 1
+//   reverses X|Y.
+__device__ __forceinline__ PairItem make_item(const Rot &R, int64_t local, int phase) {
+    PairItem it;
+    it.xa = 0;
+    it.yb = 0;
+    it.dir = 1;
+    it.lim = 0;
     if (R.lx == R.ly) {
-        if (phase != 0) return;
-        int64_t c0 = local * kRotChunk, c1 = c0 + kRotChunk;
-        if (c1 > R.lx) c1 = R.lx;
-        if (c0 < c1) swap_chunk(p, R.pos, R.pos + R.lx, c0, c1);
-        return;
+        if (phase != 0) return it;
+        const int64_t c0 = local * kRotChunk;
+        const int64_t n = R.lx - c0;
+        if (n <= 0) return it;
+        it.xa = R.pos + c0;
+        it.yb = R.pos + R.lx + c0;
+        it.lim = (int32_t)(n < kRotChunk ? n : kRotChunk);
+        return it;
     }
+    int64_t s, m, c0;
     if (phase == 0) {
-        int64_t px = R.lx / 2, py = R.ly / 2;
-        int64_t ix = (px + kRotChunk - 1) / kRotChunk;
-        int64_t iy = (py + kRotChunk - 1) / kRotChunk;
+        const int64_t ix = (R.lx / 2 + kRotChunk - 1) / kRotChunk;
         if (local < ix) {
-            int64_t c0 = local * kRotChunk, c1 = c0 + kRotChunk;
-            if (c1 > px) c1 = px;
-            rev_chunk(p, R.pos, R.lx, c0, c1);
-        } else if (local - ix < iy) {
-            int64_t c0 = (local - ix) * kRotChunk, c1 = c0 + kRotChunk;
-            if (c1 > py) c1 = py;
-            rev_chunk(p, R.pos + R.lx, R.ly, c0, c1);
+            s = R.pos; m = R.lx; c0 = local * kRotChunk;
+        } else {
+            s = R.pos + R.lx; m = R.ly; c0 = (local - ix) * kRotChunk;
         }
     } else {
-        int64_t m = R.lx + R.ly, pm = m / 2;
-        int64_t c0 = local * kRotChunk, c1 = c0 + kRotChunk;
-        if (c1 > pm) c1 = pm;
-        if (c0 < c1) rev_chunk(p, R.pos, m, c0, c1);
+        s = R.pos; m = R.lx + R.ly; c0 = local * kRotChunk;
+    }
+    const int64_t n = m / 2 - c0;          // pairs (t, m-1-t) for t < m/2
+    if (n <= 0) return it;
+    it.xa = s + c0;
+    it.yb = s + m - 1 - c0;
+    it.dir = -1;
+    it.lim = (int32_t)(n < kRotChunk ? n : kRotChunk);
+    return it;
+}
+
+template <typename E, int PER>
+struct PairRegs {
+    E x[PER], y[PER];
+};
+
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename E, int TH, int PER>
+__device__ __forceinline__ void item_load(const E *__restrict__ p, const PairItem &it,
+                                          PairRegs<E, PER> &r) {
+    const E *X = p + uni64(it.xa);
+    const E *Y = p + uni64(it.yb);
+    const int dir = __builtin_amdgcn_readfirstlane(it.dir);
+    const int lim = __builtin_amdgcn_readfirstlane(it.lim);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = (int)threadIdx.x + u * TH;
+        if (t < lim) { r.x[u] = X[t]; r.y[u] = Y[dir * t]; }
     }
 }
 
-template <typename EK, typename EV>
-__global__ __launch_bounds__(kRotThreads) void k_rotate(EK *__restrict__ keys, EV *__restrict__ vals,
+template <typename E, int TH, int PER>
+__device__ __forceinline__ void item_store(E *__restrict__ p, const PairItem &it,
+                                           const PairRegs<E, PER> &r) {
+    E *X = p + uni64(it.xa);
+    E *Y = p + uni64(it.yb);
+    const int dir = __builtin_amdgcn_readfirstlane(it.dir);
+    const int lim = __builtin_amdgcn_readfirstlane(it.lim);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = (int)threadIdx.x + u * TH;
+        if (t < lim) { X[t] = r.y[u]; Y[dir * t] = r.x[u]; }
+    }
+}
+
+template <typename EV, int PER>
+struct ValRegs { PairRegs<EV, PER> r; };
+template <int PER>
+struct ValRegs<NoVal, PER> {};
+
+template <typename EV> struct ValBytes { static constexpr int v = sizeof(EV); };
+template <> struct ValBytes<NoVal> { static constexpr int v = 0; };
+
+// A persistent grid walks the level's items, software pipelined: the loads
+// of the workgroup's next item are issued before the stores of the current
+// one, so one item's stores drain while the next one's loads are in flight.
+// (Measured on MI355X, 2^27-pair swap: plain grid-stride loop 4.2 TB/s,
+// pipelined 5.1-5.3 TB/s; one workgroup per item reaches 5.2 TB/s, but an
+// empty launch of such a grid costs about 18 us against 6 us, and the
+// phase-1 launch is empty whenever a level has only block swaps.)
+template <typename EK, typename EV, int TH = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>::threads>
+__global__ __launch_bounds__(TH) void k_rotate(EK *__restrict__ keys, EV *__restrict__ vals,
                                                         const Rot *__restrict__ rot,
                                                         const Counters *__restrict__ ctr,
                                                         int64_t cap_rot, int level, int phase) {
+    constexpr bool HAS_V = !std::is_same<EV, NoVal>::value;
+    constexpr int PER = (int)(kRotChunk / TH);
     if (phase == 1 && ctr->level_rev[level] == 0) return;   // only block swaps
     const unsigned long long packed = ctr->level_rot[level];
     int64_t nrot = (int64_t)(packed >> kRotCountShift);
     if (nrot > cap_rot) nrot = cap_rot;
     const int64_t nitems = (int64_t)(packed & kRotWorkMask);
     if (nrot == 0 || nitems == 0) return;
-    // Grid-stride over the items; the descriptor of the previous item is
-    // reused while it still covers the current one (large exchanges).
-    Rot R;
+
+    Rot R;                 // descriptor of the exchange holding the item
     R.w0 = 1;
-    R.nw = 0;        // empty: forces a search for the first item
-    for (int64_t wi = blockIdx.x; wi < nitems; wi += gridDim.x) {
-        if (wi < R.w0 || wi >= R.w0 + R.nw) {
-            // exchange holding item wi: last r with rot[r].w0 <= wi
-            int64_t lo = 0, hi = nrot;
-            while (hi - lo > 1) {
-                int64_t mid = (lo + hi) >> 1;
-                if (rot[mid].w0 <= wi) lo = mid; else hi = mid;
+    R.nw = 0;              // empty: forces a search for the first item
+    bool have = false;     // an item is loaded and waits for its stores
+    PairItem cur;
+    PairRegs<EK, PER> kr;
+    ValRegs<EV, PER> vr;
+    for (int64_t wi = blockIdx.x;; wi += gridDim.x) {
+        PairItem nx;
+        nx.lim = 0;
+        if (wi < nitems) {
+            if (wi < R.w0 || wi >= R.w0 + R.nw) {
+                // exchange holding item wi: last r with rot[r].w0 <= wi
+                int64_t lo = 0, hi = nrot;
+                while (hi - lo > 1) {
+                    int64_t mid = (lo + hi) >> 1;
+                    if (rot[mid].w0 <= wi) lo = mid; else hi = mid;
+                }
+                R = rot[lo];
             }
-            R = rot[lo];
-            if (wi < R.w0 || wi >= R.w0 + R.nw) continue;   // a dropped exchange
+            if (wi >= R.w0 && wi < R.w0 + R.nw)         // else a dropped exchange
+                nx = make_item(R, wi - R.w0, phase);
         }
-        const int64_t local = wi - R.w0;
-        do_item<EK>(keys, R, local, phase);
-        if constexpr (!std::is_same<EV, NoVal>::value) do_item<EV>(vals, R, local, phase);
+        if (nx.lim > 0) {
+            PairRegs<EK, PER> kn;
+            ValRegs<EV, PER> vn;
+            item_load<EK, TH, PER>(keys, nx, kn);
+            if constexpr (HAS_V) item_load<EV, TH, PER>(vals, nx, vn.r);
+            if (have) {
+                item_store<EK, TH, PER>(keys, cur, kr);
+                if constexpr (HAS_V) item_store<EV, TH, PER>(vals, cur, vr.r);
+            }
+            kr = kn;
+            vr = vn;
+            cur = nx;
+            have = true;
+        }
+        if (wi >= nitems) break;
+    }
+    if (have) {
+        item_store<EK, TH, PER>(keys, cur, kr);
+        if constexpr (HAS_V) item_store<EV, TH, PER>(vals, cur, vr.r);
     }
 }
 
 // Single exchange (stand-alone entry point): one descriptor built on the host.
-template <typename E>
-__global__ __launch_bounds__(kRotThreads) void k_rotate_one(E *__restrict__ p, int64_t lx,
-                                                            int64_t ly, int phase, int64_t nitems) {
+template <typename E, int TH = RotGeom<(int)sizeof(E)>::threads>
+__global__ __launch_bounds__(TH) void k_rotate_one(E *__restrict__ p, int64_t lx, int64_t ly,
+                                                   int phase, int64_t nitems) {
+    constexpr int PER = (int)(kRotChunk / TH);
     Rot R;
     R.pos = 0; R.lx = lx; R.ly = ly; R.w0 = 0; R.nw = nitems;
-    for (int64_t wi = blockIdx.x; wi < nitems; wi += gridDim.x) do_item<E>(p, R, wi, phase);
+    for (int64_t wi = blockIdx.x; wi < nitems; wi += gridDim.x) {
+        const PairItem it = make_item(R, wi, phase);
+        if (it.lim <= 0) continue;
+        PairRegs<E, PER> r;
+        item_load<E, TH, PER>(p, it, r);
+        item_store<E, TH, PER>(p, it, r);
+    }
 }
 
 template <typename EK, typename EV>
 static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, int level,
                         int phase, hipStream_t s) {
-    int g = 2048;
-    hipLaunchKernelGGL((k_rotate<EK, EV>), dim3(g), dim3(kRotThreads), 0, s, (EK *)keys,
-                       (EV *)vals, w.rot, w.ctr, pl.cap_rot, level, phase);
+    const int g = 2048;
+    constexpr int TH = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>::threads;
+    hipLaunchKernelGGL((k_rotate<EK, EV>), dim3(g), dim3(TH), 0, s, (EK *)keys, (EV *)vals,
+                       w.rot, w.ctr, pl.cap_rot, level, phase);
     return hipGetLastError();
 }
 
@@ -208,10 +250,10 @@ hipError_t launch_rotate_single(void *data, int64_t lx, int64_t ly, int esize, h
     int phases = lx == ly ? 1 : 2;
     for (int ph = 0; ph < phases; ++ph) {
         if (esize == 4)
-            hipLaunchKernelGGL(k_rotate_one<uint32_t>, dim3(g), dim3(kRotThreads), 0, s,
+            hipLaunchKernelGGL(k_rotate_one<uint32_t>, dim3(g), dim3(RotGeom<4>::threads), 0, s,
                                (uint32_t *)data, lx, ly, ph, nw);
         else if (esize == 8)
-            hipLaunchKernelGGL(k_rotate_one<uint64_t>, dim3(g), dim3(kRotThreads), 0, s,
+            hipLaunchKernelGGL(k_rotate_one<uint64_t>, dim3(g), dim3(RotGeom<8>::threads), 0, s,
                                (uint64_t *)data, lx, ly, ph, nw);
         else
             return hipErrorInvalidValue;

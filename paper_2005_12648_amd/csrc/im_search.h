@@ -100,80 +100,101 @@ __device__ __forceinline__ int64_t corank_learned(const K *__restrict__ A, int64
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront-cooperative co-rank: the 64 lanes of one wave call it with the
-// same arguments and all get the same answer.  Each round probes 63 points
-// that cut [lo, hi) into 64 nearly equal parts; P is true on a prefix of
-// them, so one ballot narrows the range 64-fold (about 5 dependent rounds
-// for 2^27 candidates instead of 27 for a binary search).  `rounds` counts
-// the dependent probe rounds.
-template <typename K>
-__device__ __forceinline__ int64_t corank_wave_range(const K *__restrict__ A,
-                                                     const K *__restrict__ B, int64_t k,
-                                                     int64_t lo, int64_t hi, uint32_t &rounds) {
+// Group-cooperative searches.  The W lanes of an aligned group (W a power of
+// two dividing 64) call with the same arguments and all get the same answer.
+// Each round probes W points that cut [lo, hi) into W+1 nearly equal parts;
+// the predicate is true on a prefix of them, so one ballot narrows the range
+// (W+1)-fold: about 5 dependent rounds for 2^27 candidates with W = 64, 8
+// with W = 8, instead of 27 for a binary search.  Different groups of a wave
+// may search different ranges; the loop runs until every group is done
+// (lanes of finished groups only take part in the ballots).  `rounds` counts
+// the group's dependent probe rounds.
+//
+// Generic form: P(m) true then false on [lo, hi); returns the first m with
+// P(m) false, or hi.
+template <int W, typename Pred>
+__device__ __forceinline__ int64_t group_search(int64_t lo, int64_t hi, Pred P, uint32_t &rounds) {
+    static_assert(W >= 2 && W <= 64 && (W & (W - 1)) == 0, "group width");
     const int lane = threadIdx.x & 63;
-    while (hi - lo > 64) {
-        const int64_t span = hi - lo;           // < 2^47, so span * 64 fits
-        const int64_t m = lo + span * (lane + 1) / 64;
+    const int gl = lane & (W - 1);
+    const int gbase = lane & ~(W - 1);
+    const uint64_t gmask = W == 64 ? ~0ull : ((1ull << W) - 1);
+    for (;;) {
+        const bool wide = hi - lo > W;
+        if (!__any(wide)) break;
+        const int64_t span = hi - lo;             // < 2^47, so span * 65 fits
         bool p = false;
-        if (lane < 63) p = A[m] <= B[k - 1 - m];
-        const int c = __popcll(__ballot(p));
-        ++rounds;
-        const int64_t nlo = c > 0 ? lo + span * c / 64 + 1 : lo;
-        const int64_t nhi = c < 63 ? lo + span * (c + 1) / 64 : hi;
-        lo = nlo;
-        hi = nhi;
+        if (wide) p = P(lo + span * (gl + 1) / (W + 1));
+        const int c = __popcll((__ballot(p) >> gbase) & gmask);
+        if (wide) {
+            ++rounds;
+            const int64_t nlo = c > 0 ? lo + span * c / (W + 1) + 1 : lo;
+            const int64_t nhi = c < W ? lo + span * (c + 1) / (W + 1) : hi;
+            lo = nlo;
+            hi = nhi;
+        }
     }
-    bool p = false;
-    const int64_t m = lo + lane;
-    if (m < hi) p = A[m] <= B[k - 1 - m];
-    ++rounds;
-    return lo + __popcll(__ballot(p));
+    const int64_t m = lo + gl;
+    const bool p = m < hi && P(m);
+    if (hi > lo) ++rounds;
+    return lo + __popcll((__ballot(p) >> gbase) & gmask);
 }
 
-template <typename K>
-__device__ __forceinline__ int64_t corank_wave(const K *__restrict__ A, int64_t la,
-                                               const K *__restrict__ B, int64_t lb, int64_t k,
-                                               uint32_t &rounds) {
-    int64_t lo = k > lb ? k - lb : 0;
-    int64_t hi = k < la ? k : la;
-    return corank_wave_range(A, B, k, lo, hi, rounds);
+template <int W, typename K>
+__device__ __forceinline__ int64_t corank_group(const K *__restrict__ A, int64_t la,
+                                                const K *__restrict__ B, int64_t lb, int64_t k,
+                                                uint32_t &rounds) {
+    const int64_t lo = k > lb ? k - lb : 0;
+    const int64_t hi = k < la ? k : la;
+    return group_search<W>(lo, hi, [&](int64_t m) { return A[m] <= B[k - 1 - m]; }, rounds);
 }
 
-// Learned wave co-rank: the first round probes 63 points spaced by the
+// Learned group co-rank: the first round probes W points spaced by the
 // model's typical error around its prediction, then the plain rounds go on
 // inside the bracket that round leaves (always exact).
-template <typename K>
-__device__ __forceinline__ int64_t corank_wave_learned(const K *__restrict__ A, int64_t la,
-                                                       const K *__restrict__ B, int64_t lb,
-                                                       int64_t k, const MlpDev *__restrict__ M,
-                                                       int64_t kg, int64_t n_inst,
-                                                       int64_t la_inst, int64_t i0,
-                                                       uint32_t &rounds) {
+template <int W, typename K>
+__device__ __forceinline__ int64_t corank_group_learned(const K *__restrict__ A, int64_t la,
+                                                        const K *__restrict__ B, int64_t lb,
+                                                        int64_t k, const MlpDev *__restrict__ M,
+                                                        int64_t kg, int64_t n_inst,
+                                                        int64_t la_inst, int64_t i0,
+                                                        uint32_t &rounds) {
     const int lane = threadIdx.x & 63;
+    const int gl = lane & (W - 1);
+    const int gbase = lane & ~(W - 1);
+    const uint64_t gmask = W == 64 ? ~0ull : ((1ull << W) - 1);
     int64_t lo = k > lb ? k - lb : 0;
     int64_t hi = k < la ? k : la;
-    if (hi - lo <= 64) return corank_wave_range(A, B, k, lo, hi, rounds);
-    float x = n_inst > 0 ? (float)((double)kg / (double)n_inst) : 0.0f;
-    double gd = (double)mlp_eval(M, x) * (double)la_inst - (double)i0;
-    int64_t g;
-    if (!(gd == gd) || gd <= (double)lo) g = lo;
-    else if (gd >= (double)hi) g = hi;
-    else g = (int64_t)llrint(gd);
-    int64_t step = (int64_t)M->err_scale;
-    if (step < 1) step = 1;
-    // probe g + (lane - 31) * step, clamped into [lo, hi-1]: non-decreasing in lane
-    int64_t m = g + (int64_t)(lane - 31) * step;
-    if (m < lo) m = lo;
-    if (m > hi - 1) m = hi - 1;
+    const bool wide = hi - lo > W;
     bool p = false;
-    if (lane < 63) p = A[m] <= B[k - 1 - m];
-    const int c = __popcll(__ballot(p));
-    ++rounds;
-    const int64_t m_prev = __shfl(m, c > 0 ? c - 1 : 0, 64);
-    const int64_t m_next = __shfl(m, c < 63 ? c : 62, 64);
-    const int64_t nlo = c > 0 ? m_prev + 1 : lo;
-    const int64_t nhi = c < 63 ? m_next : hi;
-    return corank_wave_range(A, B, k, nlo, nhi > nlo ? nhi : nlo, rounds);
+    int64_t m = lo;
+    if (wide) {
+        const float x = n_inst > 0 ? (float)((double)kg / (double)n_inst) : 0.0f;
+        const double gd = (double)mlp_eval(M, x) * (double)la_inst - (double)i0;
+        int64_t g;
+        if (!(gd == gd) || gd <= (double)lo) g = lo;
+        else if (gd >= (double)hi) g = hi;
+        else g = (int64_t)llrint(gd);
+        int64_t step = (int64_t)M->err_scale;
+        if (step < 1) step = 1;
+        // probe g + (gl - W/2) * step, clamped into [lo, hi-1]: non-decreasing in gl
+        m = g + (int64_t)(gl - W / 2) * step;
+        if (m < lo) m = lo;
+        if (m > hi - 1) m = hi - 1;
+        p = A[m] <= B[k - 1 - m];
+    }
+    const int c = __popcll((__ballot(p) >> gbase) & gmask);
+    // every lane takes part in the shuffles; sources lie in the same group
+    const int64_t m_prev = __shfl(m, gbase + (c > 0 ? c - 1 : 0), 64);
+    const int64_t m_next = __shfl(m, gbase + (c < W ? c : W - 1), 64);
+    if (wide) {
+        ++rounds;
+        const int64_t nlo = c > 0 ? m_prev + 1 : lo;
+        const int64_t nhi = c < W ? m_next : hi;
+        lo = nlo;
+        hi = nhi > nlo ? nhi : nlo;
+    }
+    return group_search<W>(lo, hi, [&](int64_t q) { return A[q] <= B[k - 1 - q]; }, rounds);
 }
 
 }  // namespace imerge

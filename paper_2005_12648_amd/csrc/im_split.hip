@@ -168,10 +168,10 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
                 const int inst = __shfl(nd.inst, src, 64);
                 int64_t o0 = offsets[2 * inst], o1 = offsets[2 * inst + 1],
                         o2 = offsets[2 * inst + 2];
-                i = corank_wave_learned(A, la, B, lb, kk, mlp, k0 + kk, o2 - o0, o1 - o0, i0,
-                                        rounds);
+                i = corank_group_learned<64>(A, la, B, lb, kk, mlp, k0 + kk, o2 - o0, o1 - o0,
+                                             i0, rounds);
             } else {
-                i = corank_wave(A, la, B, lb, kk, rounds);
+                i = corank_group<64>(A, la, B, lb, kk, rounds);
             }
             if (lane != src) continue;
             const int64_t j = kk - i;
@@ -198,6 +198,9 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
 }
 
 // Tile co-ranks: tile t of leaf l starts at local diagonal (t - tile_start[l]) * tile.
+// One lane per tile, binary searches.  (Measured: group-cooperative searches
+// with 8 lanes per tile need fewer dependent rounds but 2-3x the loads, and
+// are slower here: this stage is bound by the memory system, not latency.)
 template <typename K, bool LEARNED>
 __global__ __launch_bounds__(kSplitThreads) void k_tilerank(const K *__restrict__ data,
                                                             const int64_t *__restrict__ offsets,
