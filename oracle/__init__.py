@@ -17,6 +17,13 @@ Contents and the passage each one follows:
   and circular shifting with its cycle/move counters (Sec. 3.4 proof, Sec. 3.5).
 * :func:`sort_keys` -- the merge-sort driver's result is the sorted input; the
   library sort is the definition.
+* :func:`find_median` -- FindMedian, Alg. 1 (Sec. 3.3), step by step, with the
+  reading of its garbled loop stated in ``oracle.c``.
+* :func:`divide` -- the recursive division of Sec. 3 (as Alg. 3 recurses on
+  A0|B0 and A1|B1) down to 2^depth pairs, with FindMedian or the exact co-rank
+  at the middle rank as the split; returns the pair sizes.  No data moves: the
+  pairs are ranges of the original A and B.
+* :func:`merge_par` -- the stable merge on all host cores (timing only).
 * :class:`MLP64` -- fp64 forward pass, MSE loss, closed-form gradients and one
   Adam step of the 1->32->1 ReLU network used to predict co-ranks.  The paper
   has no learned component: input x = k/N, target t = i(k)/L_A, mean squared
@@ -44,7 +51,8 @@ def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with gcc (no HIP headers involved)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp], check=True)
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp],
+                       check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -66,6 +74,12 @@ def _load():
             f = getattr(lib, "orc_corank_" + t)
             f.argtypes = [vp, i64, vp, i64, vp, i64, vp]
             f.restype = None
+            f = getattr(lib, "orc_find_median_" + t)
+            f.argtypes = [vp, i64, vp, i64, vp, vp]
+            f.restype = None
+            f = getattr(lib, "orc_merge_par_" + t)
+            f.argtypes = [vp, i64, i64]
+            f.restype = ctypes.c_int
         lib.orc_rotate_def.argtypes = [vp, i64, i64]
         lib.orc_rotate_def.restype = ctypes.c_int
         lib.orc_rotate_ls.argtypes = [vp, i64, i64]
@@ -156,6 +170,58 @@ def rotate_cs(x: np.ndarray, lx: int):
     mov = ctypes.c_int64(0)
     _load().orc_rotate_cs(d.ctypes.data, lx, d.size - lx, ctypes.byref(cyc), ctypes.byref(mov))
     return d, int(cyc.value), int(mov.value)
+
+
+def merge_par(data: np.ndarray, la: int):
+    """merge() computed by all host cores; returns (result, threads used)."""
+    out = np.ascontiguousarray(data).copy()
+    n = out.shape[0]
+    if not 0 <= la <= n:
+        raise ValueError("la out of range")
+    rc = getattr(_load(), "orc_merge_par_" + _suffix(out))(out.ctypes.data, la, n - la)
+    if rc < 0:
+        raise MemoryError("oracle merge_par: allocation failed")
+    return out, int(rc)
+
+
+def find_median(a: np.ndarray, b: np.ndarray):
+    """FindMedian (Alg. 1) of the sorted runs a and b: returns (p_A, p_B)."""
+    a = np.ascontiguousarray(a)
+    b = np.ascontiguousarray(b)
+    if a.dtype != b.dtype:
+        raise TypeError("a and b must share a dtype")
+    pa = ctypes.c_int64(0)
+    pb = ctypes.c_int64(0)
+    getattr(_load(), "orc_find_median_" + _suffix(a))(
+        a.ctypes.data, a.size, b.ctypes.data, b.size, ctypes.byref(pa), ctypes.byref(pb))
+    return int(pa.value), int(pb.value)
+
+
+def divide(a: np.ndarray, b: np.ndarray, depth: int, method: str = "corank"):
+    """Split (a, b) recursively into 2**depth pairs (A_p, B_p), in order.
+
+    method "corank": the exact split at the middle rank floor((|A|+|B|)/2)
+    (ties take A); "findmedian": Alg. 1.  Returns an int64 array of shape
+    (2**depth, 2) holding (|A_p|, |B_p|)."""
+    if method not in ("corank", "findmedian"):
+        raise ValueError("method")
+    a = np.ascontiguousarray(a)
+    b = np.ascontiguousarray(b)
+    nodes = [(0, a.size, 0, b.size)]            # (a_off, la, b_off, lb)
+    for _ in range(depth):
+        nxt = []
+        for ao, la, bo, lb in nodes:
+            sa, sb = a[ao:ao + la], b[bo:bo + lb]
+            if method == "corank":
+                k = (la + lb) // 2
+                i = int(corank(sa, sb, [k])[0]) if la + lb > 0 else 0
+                j = k - i
+            else:
+                i, j = find_median(sa, sb) if la + lb > 0 else (0, 0)
+            nxt.append((ao, i, bo, j))
+            nxt.append((ao + i, la - i, bo + j, lb - j))
+        nodes = nxt
+    return np.array([(la, lb) for _, la, _, lb in nodes], dtype=np.int64)
 
 
 def sort_keys(x: np.ndarray) -> np.ndarray:

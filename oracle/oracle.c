@@ -33,12 +33,30 @@
  *                   i -> i+L_B (A side) / i -> i-L_A (B side) starting at
  *                   0, 1, ..., until every element has been placed once.
  *
+ *   - FindMedian (Sec. 3.3, Alg. 1): the paper's double binary search for
+ *               a pivot pair that splits A and B into A0 A1, B0 B1 with
+ *               A0 <= B1, B0 <= A1 and |A0|+|B0| close to |A1|+|B1|.  Taken
+ *               step by step from Alg. 1; the loop as printed tests p_A, p_B
+ *               before first setting them, and after a stop on an equal probe
+ *               it recomputes midpoints (which can give an invalid split when
+ *               keys repeat).  Reading used here: the probes start at the
+ *               midpoints of A and B (the text of Sec. 3.3 says so), and a
+ *               stop on an equal probe returns that probe pair.
+ *   - merge_par: the same stable merge computed by all host cores (OpenMP):
+ *               the output is cut at equal ranks whose co-ranks come from one
+ *               walk of the two-finger merge, each piece is merged into the
+ *               fresh buffer, then copied back.  Only for timing beside the
+ *               GPU; its result equals merge().
+ *
  * Error behaviour: every function trusts its caller (the Python wrapper
  * validates shapes); on allocation failure the merge functions return -1.
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Stable two-finger merge (problem statement, Sec. 1).  Ties take A.        */
@@ -209,3 +227,95 @@ int orc_rotate_cs(int64_t *data, int64_t la, int64_t lb,
     *moves_out = moves;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* FindMedian (Sec. 3.3, Alg. 1), with the reading stated at the top.       */
+/* ------------------------------------------------------------------------ */
+#define DEFINE_FIND_MEDIAN(NAME, KT)                                           \
+void NAME(const KT *A, int64_t la, const KT *B, int64_t lb,                     \
+          int64_t *pa_out, int64_t *pb_out)                                     \
+{                                                                               \
+    /* special cases tested first (Alg. 1, first two tests) */                 \
+    if (la == 0 || lb == 0 || A[la - 1] <= B[0]) {                              \
+        *pa_out = la; *pb_out = 0; return;                                      \
+    }                                                                           \
+    if (!(A[0] <= B[lb - 1])) { *pa_out = 0; *pb_out = lb; return; }            \
+    int64_t left_a = 0, limit_a = la, left_b = 0, limit_b = lb;                 \
+    int64_t p_a = la / 2, p_b = lb / 2;     /* probes start at the middles */   \
+    while (left_a < limit_a && left_b < limit_b && A[p_a] != B[p_b]) {          \
+        p_a = (limit_a - left_a) / 2 + left_a;                                  \
+        p_b = (limit_b - left_b) / 2 + left_b;                                  \
+        int64_t a0 = p_a, a1 = la - p_a, b0 = p_b, b1 = lb - p_b;               \
+        if (A[p_a] < B[p_b]) {                                                  \
+            if (a0 + b0 < a1 + b1) left_a = p_a + 1;                            \
+            else limit_b = p_b;                                                 \
+        } else {                                                                \
+            if (a0 + b0 < a1 + b1) left_b = p_b + 1;                            \
+            else limit_a = p_a;                                                 \
+        }                                                                       \
+    }                                                                           \
+    if (left_a < limit_a && left_b < limit_b) {                                 \
+        /* stopped because A[p_a] == B[p_b]: that probe pair is the pivot */    \
+        *pa_out = p_a; *pb_out = p_b; return;                                   \
+    }                                                                           \
+    *pa_out = (limit_a - left_a) / 2 + left_a;                                  \
+    *pb_out = (limit_b - left_b) / 2 + left_b;                                  \
+}
+
+DEFINE_FIND_MEDIAN(orc_find_median_i32, int32_t)
+DEFINE_FIND_MEDIAN(orc_find_median_u32, uint32_t)
+DEFINE_FIND_MEDIAN(orc_find_median_i64, int64_t)
+DEFINE_FIND_MEDIAN(orc_find_median_u64, uint64_t)
+
+/* ------------------------------------------------------------------------ */
+/* All-cores stable merge (timing only): cuts at ranks k_t = t*N/P, co-ranks */
+/* from one walk of the two-finger merge, pieces merged in parallel into a   */
+/* fresh buffer, parallel copy back.  Returns the threads used, -1 on        */
+/* allocation failure.                                                       */
+/* ------------------------------------------------------------------------ */
+#define DEFINE_MERGE_PAR(NAME, KT)                                             \
+int NAME(KT *data, int64_t la, int64_t lb)                                      \
+{                                                                               \
+    int64_t n = la + lb;                                                        \
+    int P = 1;                                                                  \
+    _Pragma("omp parallel") { _Pragma("omp single") P = OMP_THREADS(); }       \
+    if (n == 0) return P;                                                       \
+    KT *out = (KT *)malloc((size_t)n * sizeof(KT));                             \
+    int64_t *ia = (int64_t *)malloc((size_t)(P + 1) * sizeof(int64_t));        \
+    if (!out || !ia) { free(out); free(ia); return -1; }                        \
+    const KT *A = data, *B = data + la;                                         \
+    /* one walk of the merge gives the co-rank of every cut */                  \
+    int64_t i = 0, j = 0;                                                       \
+    for (int t = 0; t <= P; t++) {                                              \
+        int64_t k = (int64_t)((double)n * t / P);                               \
+        if (t == P) k = n;                                                      \
+        while (i + j < k) {                                                     \
+            if (j >= lb || (i < la && A[i] <= B[j])) i++; else j++;             \
+        }                                                                       \
+        ia[t] = i;                                                              \
+    }                                                                           \
+    _Pragma("omp parallel for schedule(static)")                                \
+    for (int t = 0; t < P; t++) {                                               \
+        int64_t k0 = (int64_t)((double)n * t / P);                              \
+        int64_t k1 = (t + 1 == P) ? n : (int64_t)((double)n * (t + 1) / P);     \
+        int64_t x = ia[t], y = k0 - ia[t], o = k0;                              \
+        while (o < k1) {                                                        \
+            if (y >= lb || (x < la && A[x] <= B[y])) out[o++] = A[x++];         \
+            else out[o++] = B[y++];                                             \
+        }                                                                       \
+    }                                                                           \
+    _Pragma("omp parallel for schedule(static)")                                \
+    for (int64_t q = 0; q < n; q++) data[q] = out[q];                           \
+    free(out); free(ia);                                                        \
+    return P;                                                                   \
+}
+
+#ifdef _OPENMP
+#define OMP_THREADS() omp_get_num_threads()
+#else
+#define OMP_THREADS() 1
+#endif
+DEFINE_MERGE_PAR(orc_merge_par_i32, int32_t)
+DEFINE_MERGE_PAR(orc_merge_par_u32, uint32_t)
+DEFINE_MERGE_PAR(orc_merge_par_i64, int64_t)
+DEFINE_MERGE_PAR(orc_merge_par_u64, uint64_t)

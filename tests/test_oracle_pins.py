@@ -238,3 +238,102 @@ def test_adam_first_step_closed_form():
     new, mo, ve = oracle.MLP64.adam_step(th, g, np.zeros(4), np.zeros(4), 1, lr=0.1)
     assert np.allclose(new, -0.1 * g / (np.abs(g) + 1e-8))
     assert np.allclose(mo, 0.1 * g) and np.allclose(ve, 0.001 * g * g)
+
+
+# ------------------------------------------------------------- FindMedian
+def _fm_cases():
+    cases, cur = [], None
+    for line in open(os.path.join(GOLD, "findmedian_trace.txt")):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "CASE":
+            ib = f.index("B")
+            cur = (np.array(f[2:ib], dtype=np.int64), np.array(f[ib + 1:], dtype=np.int64))
+        elif f[0] == "RESULT":
+            cases.append((cur[0], cur[1], (int(f[1]), int(f[2]))))
+    return cases
+
+
+def test_golden_findmedian_trace():
+    cases = _fm_cases()
+    assert len(cases) == 4
+    for a, b, want in cases:
+        assert oracle.find_median(a, b) == want
+
+
+def _fm_valid(a, b, pa, pb):
+    # Sec. 3.3: A0 <= B1 and B0 <= A1 (every element of the left halves is at
+    # most every element of the right halves)
+    if not (0 <= pa <= a.size and 0 <= pb <= b.size):
+        return False
+    if pa > 0 and pb < b.size and a[pa - 1] > b[pb]:
+        return False
+    if pb > 0 and pa < a.size and b[pb - 1] > a[pa]:
+        return False
+    return True
+
+
+def test_findmedian_valid_exhaustive_small():
+    # every pair of sorted runs of length <= 5 over keys {0, 1, 2, 3}
+    runs = [np.array(c, dtype=np.int32) for n in range(6)
+            for c in itertools.combinations_with_replacement(range(4), n)]
+    for a in runs:
+        for b in runs:
+            pa, pb = oracle.find_median(a, b)
+            assert _fm_valid(a, b, pa, pb), (a, b, pa, pb)
+
+
+def test_findmedian_special_cases_and_interleaved():
+    r = np.random.default_rng(5)
+    for _ in range(200):
+        la, lb = r.integers(1, 50, size=2)
+        a = np.sort(r.integers(0, 100, la)).astype(np.int64)
+        b = np.sort(r.integers(100, 200, lb)).astype(np.int64)
+        assert oracle.find_median(a, b) == (la, 0)       # A before B
+        assert oracle.find_median(b, a) == (0, la)       # B before A
+    # equal-length perfectly interleaved runs: the split is exactly balanced
+    for n in range(1, 200):
+        a = np.arange(n, dtype=np.int64) * 2
+        b = a + 1
+        pa, pb = oracle.find_median(a, b)
+        assert pa + pb == n and _fm_valid(a, b, pa, pb)
+
+
+def test_divide_pairs_merge_to_sorted():
+    # the pairs of either division, merged one by one and concatenated, give
+    # the sorted input (keys); the co-rank division is balanced to one element
+    r = np.random.default_rng(6)
+    for trial in range(20):
+        la, lb = r.integers(0, 3000, size=2)
+        hi = 20 if trial % 2 else 2 ** 31
+        a = np.sort(r.integers(0, hi, la)).astype(np.int32)
+        b = np.sort(r.integers(0, hi, lb)).astype(np.int32)
+        want = np.sort(np.concatenate([a, b]))
+        for method in ("corank", "findmedian"):
+            for depth in (1, 3, 5):
+                sizes = oracle.divide(a, b, depth, method)
+                assert sizes.shape == (2 ** depth, 2)
+                assert sizes[:, 0].sum() == la and sizes[:, 1].sum() == lb
+                ao = np.concatenate([[0], np.cumsum(sizes[:, 0])])
+                bo = np.concatenate([[0], np.cumsum(sizes[:, 1])])
+                parts = []
+                for p in range(2 ** depth):
+                    pa, pb = a[ao[p]:ao[p + 1]], b[bo[p]:bo[p + 1]]
+                    parts.append(oracle.merge(np.concatenate([pa, pb]), pa.size))
+                got = np.concatenate(parts) if parts else np.zeros(0, np.int32)
+                assert np.array_equal(got, want), (method, depth)
+                if method == "corank":
+                    tot = sizes.sum(axis=1)
+                    assert tot.max() - tot.min() <= 1
+
+
+def test_merge_par_equals_merge():
+    r = np.random.default_rng(7)
+    for n, la in [(0, 0), (1, 1), (10, 3), (100001, 40000), (300000, 150000)]:
+        d = r.integers(0, 1000, n).astype(np.int64)
+        d[:la].sort()
+        d[la:].sort()
+        got, threads = oracle.merge_par(d, la)
+        assert threads >= 1
+        assert np.array_equal(got, oracle.merge(d, la))
