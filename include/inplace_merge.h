@@ -84,6 +84,7 @@ typedef struct {
     int64_t searches;        /* split searches performed (device)             */
     int32_t leaf_config;     /* leaf-merge configuration used (0..3)           */
     int32_t leaf_grid;       /* resident workgroups of the leaf merge          */
+    int64_t split_fallbacks; /* FindMedian splits replaced by co-rank (device) */
 } im_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -180,7 +181,51 @@ int inplace_merge_autotune(const void *data, const int64_t *d_offsets, int64_t n
                            int val_dtype, int reps, double *ms_out, int *chosen,
                            hipStream_t stream);
 
-/* In-place merge sort of data[0, n): each tile is sorted in LDS, then
+/* ---------------------------------------------------------------------- */
+/* Method variants and comparators (the paper's alternatives).             */
+/* ---------------------------------------------------------------------- */
+#define IM_SPLIT_CORANK 0      /* exact co-rank split (Sec. 3.1, "optimal")      */
+#define IM_SPLIT_FINDMEDIAN 1  /* FindMedian double binary search (Alg. 1)     */
+#define IM_ROTATE_LS 0         /* linear shifting: block swap / reversals       */
+#define IM_ROTATE_CS 1         /* circular shifting: cycles (Sec. 3.4)          */
+
+/* inplace_merge() with the split and exchange methods chosen (keys only).
+ * IM_SPLIT_FINDMEDIAN splits every division node with FindMedian (Sec. 3.3,
+ * Alg. 1; probes start at the middles and a stop on an equal probe returns
+ * that pair); a node whose FindMedian split is invalid or leaves a child
+ * larger than 9/16 of the node is split by co-rank instead (counted in
+ * im_stats.split_fallbacks), which keeps the level count bounded.
+ * FindMedian splits satisfy A0 <= B1 and B0 <= A1, so the result equals the
+ * stable merge for keys (payloads could not tell equal keys apart: no kv
+ * form).  IM_ROTATE_CS does every exchange by circular shifting (Sec. 3.4):
+ * gcd(|X|+|Y|, |Y|) cycles, each element moved once, strided access; it
+ * needs a stash of 2*(L_A+L_B)/256 elements in the workspace. */
+int inplace_merge_variant(void *data, int64_t L_A, int64_t L_B, int dtype, int split_method,
+                          int rot_method, hipStream_t stream);
+
+/* Division without data movement (the pivot searches of Sec. 3 applied
+ * recursively, as in Alg. 3): split data[0,L_A) | data[L_A,L_A+L_B) into
+ * 2^depth pairs (depth 0..24) with method IM_SPLIT_CORANK (exact co-rank at
+ * the middle rank of each node) or IM_SPLIT_FINDMEDIAN (Alg. 1).  d_sizes
+ * (device int64[2 * 2^depth]) receives (|A_p|, |B_p|) for every pair in
+ * order.  Uses stream-ordered temporary memory. */
+int im_divide(const void *data, int64_t L_A, int64_t L_B, int dtype, int method, int depth,
+              int64_t *d_sizes, hipStream_t stream);
+
+/* Partition exchange X|Y -> Y|X by circular shifting (Sec. 3.4): the
+ * comparator of im_rotate.  elem_bytes 4 or 8; stream-ordered stash. */
+int im_rotate_cs(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t stream);
+
+/* The classic out-of-place merge (the paper's external-buffer comparator):
+ * out = stable merge of in[0,L_A) and in[L_A,L_A+L_B); in and out must not
+ * overlap.  inplace_merge_buffered() allocates the buffer, merges into it,
+ * copies back and frees it (allocation, copy and free included, as in the
+ * paper's comparison). */
+int merge_out_of_place(const void *in, void *out, int64_t L_A, int64_t L_B, int dtype,
+                       hipStream_t stream);
+int inplace_merge_buffered(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream);
+
+/* In-place merge sort of data[0, n): each tile is sorted in LDS, then/* In-place merge sort of data[0, n): each tile is sorted in LDS, then
  * bottom-up passes of the batched merge double the sorted run length; the
  * unpaired last run of a pass is carried over unchanged. */
 int inplace_merge_sort(void *data, int64_t n, int dtype, hipStream_t stream);

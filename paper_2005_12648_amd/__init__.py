@@ -26,6 +26,8 @@ __all__ = [
     "corank", "rotate", "fetch_stats", "workspace_bytes", "set_workspace",
     "MergeModel", "MLP_HIDDEN", "MLP_PARAMS", "profile", "profile_read", "STAGES",
     "MergeGraph", "set_config", "autotune", "LEAF_CONFIGS",
+    "inplace_merge_variant", "divide", "rotate_cs", "merge_out_of_place",
+    "inplace_merge_buffered", "SPLIT_CORANK", "SPLIT_FINDMEDIAN", "ROTATE_LS", "ROTATE_CS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +37,8 @@ _lib = None
 MLP_HIDDEN = 32
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
 LEAF_CONFIGS = 4
+SPLIT_CORANK, SPLIT_FINDMEDIAN = 0, 1
+ROTATE_LS, ROTATE_CS = 0, 1
 
 # im_dtype codes of the C ABI
 _DT = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3}
@@ -63,6 +67,7 @@ class _Stats(ctypes.Structure):
         ("reversed_elems", ctypes.c_int64), ("leaf_elems", ctypes.c_int64),
         ("search_probes", ctypes.c_int64), ("searches", ctypes.c_int64),
         ("leaf_config", ctypes.c_int32), ("leaf_grid", ctypes.c_int32),
+        ("split_fallbacks", ctypes.c_int64),
     ]
 
 
@@ -114,6 +119,11 @@ def load():
         "im_graph_cooperative": [vp],
         "im_graph_destroy": [vp],
         "inplace_merge_set_config": [c_int],
+        "inplace_merge_variant": [vp, i64, i64, c_int, c_int, c_int, vp],
+        "im_divide": [vp, i64, i64, c_int, c_int, c_int, vp, vp],
+        "im_rotate_cs": [vp, i64, i64, c_int, vp],
+        "merge_out_of_place": [vp, vp, i64, i64, c_int, vp],
+        "inplace_merge_buffered": [vp, i64, i64, c_int, vp],
         "inplace_merge_autotune": [vp, vp, i64, i64, i64, c_int, c_int, c_int,
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int), vp],
     }
@@ -254,6 +264,80 @@ def rotate(data: torch.Tensor, lx: int, stream=None) -> torch.Tensor:
     with torch.cuda.device(data.device):
         _check(load().im_rotate(ctypes.c_void_p(data.data_ptr()), lx, n - lx,
                                 data.element_size(), _stream(stream)))
+    return data
+
+
+def inplace_merge_variant(data: torch.Tensor, la: int, split: int = SPLIT_CORANK,
+                          rotation: int = ROTATE_LS, stream=None) -> torch.Tensor:
+    """In-place merge with the split (co-rank / FindMedian) and exchange (linear /
+    circular shifting) methods of the paper chosen; keys only."""
+    _dev_tensor(data, "data")
+    n = data.numel()
+    if not 0 <= la <= n:
+        raise ValueError("la out of range")
+    with torch.cuda.device(data.device):
+        _check(load().inplace_merge_variant(ctypes.c_void_p(data.data_ptr()), la, n - la,
+                                            _key_code(data), int(split), int(rotation),
+                                            _stream(stream)))
+    return data
+
+
+def divide(data: torch.Tensor, la: int, depth: int, method: int = SPLIT_CORANK,
+           stream=None) -> torch.Tensor:
+    """Pair sizes (|A_p|, |B_p|) of the recursive division into 2**depth pairs
+    (no data movement); int64 device tensor of shape (2**depth, 2)."""
+    _dev_tensor(data, "data")
+    n = data.numel()
+    if not 0 <= la <= n:
+        raise ValueError("la out of range")
+    out = torch.empty((1 << depth, 2), dtype=torch.int64, device=data.device)
+    with torch.cuda.device(data.device):
+        _check(load().im_divide(ctypes.c_void_p(data.data_ptr()), la, n - la, _key_code(data),
+                                int(method), int(depth), ctypes.c_void_p(out.data_ptr()),
+                                _stream(stream)))
+    return out
+
+
+def rotate_cs(data: torch.Tensor, lx: int, stream=None) -> torch.Tensor:
+    """Partition exchange by circular shifting: data = X|Y becomes Y|X."""
+    _dev_tensor(data, "data")
+    n = data.numel()
+    if not 0 <= lx <= n:
+        raise ValueError("lx out of range")
+    with torch.cuda.device(data.device):
+        _check(load().im_rotate_cs(ctypes.c_void_p(data.data_ptr()), lx, n - lx,
+                                   data.element_size(), _stream(stream)))
+    return data
+
+
+def merge_out_of_place(data: torch.Tensor, la: int, out: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    """Stable merge of data[:la] and data[la:] into a separate tensor."""
+    _dev_tensor(data, "data")
+    n = data.numel()
+    if not 0 <= la <= n:
+        raise ValueError("la out of range")
+    if out is None:
+        out = torch.empty_like(data)
+    _dev_tensor(out, "out")
+    if out.numel() != n or out.dtype != data.dtype:
+        raise ValueError("out must match data")
+    with torch.cuda.device(data.device):
+        _check(load().merge_out_of_place(ctypes.c_void_p(data.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), la, n - la,
+                                         _key_code(data), _stream(stream)))
+    return out
+
+
+def inplace_merge_buffered(data: torch.Tensor, la: int, stream=None) -> torch.Tensor:
+    """Merge through a temporary buffer (allocate, merge, copy back, free)."""
+    _dev_tensor(data, "data")
+    n = data.numel()
+    if not 0 <= la <= n:
+        raise ValueError("la out of range")
+    with torch.cuda.device(data.device):
+        _check(load().inplace_merge_buffered(ctypes.c_void_p(data.data_ptr()), la, n - la,
+                                             _key_code(data), _stream(stream)))
     return data
 
 

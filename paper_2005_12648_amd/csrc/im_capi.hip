@@ -191,6 +191,9 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
         ++lv;
     }
     pl->max_levels = lv;
+    pl->split_method = kSplitCorank;
+    pl->rot_method = kRotLS;
+    pl->cap_stash = 2 * (total / kCsSeg) + 16;
     int64_t per = total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
     pl->cap_nodes = std::max<int64_t>(n_inst, 2 * per) + 16;
     pl->cap_rot = pl->cap_nodes;
@@ -218,6 +221,12 @@ size_t carve(const Plan &pl, int64_t flag_slots, void *base, Work *w) {
     x.tile_leaf = (int32_t *)take(sizeof(int32_t) * pl.cap_tiles);
     x.tile_dep = (int32_t *)take(sizeof(int32_t) * 2 * pl.cap_tiles);
     x.offsets1 = (int64_t *)take(sizeof(int64_t) * 4);
+    x.cs_stash_k = nullptr;
+    x.cs_stash_v = nullptr;
+    if (pl.rot_method == kRotCS) {
+        x.cs_stash_k = take((size_t)8 * pl.cap_stash);
+        x.cs_stash_v = take((size_t)8 * pl.cap_stash);
+    }
     if (w) *w = x;
     return off;
 }
@@ -338,7 +347,8 @@ void record_stats(const Plan &pl, const Work &w) {
 // cfg_override >= 0 forces a leaf configuration (autotuner).
 int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
                  int64_t n_inst, int64_t total, int64_t max_inst, int64_t la, int64_t lb,
-                 const MlpDev *mlp, hipStream_t s, int cfg_override = -1) {
+                 const MlpDev *mlp, hipStream_t s, int cfg_override = -1,
+                 int split_method = kSplitCorank, int rot_method = kRotLS) {
     int dev = 0;
     DevState *ds = dev_state(&dev);
     if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
@@ -348,6 +358,8 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     Plan pl;
     if (!make_plan(ds, ek, ev, n_inst, total, max_inst, cfg, &pl))
         return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
+    pl.split_method = split_method;
+    pl.rot_method = rot_method;
     size_t need = carve(pl, ds->flag_cap, nullptr, nullptr);
     void *base = nullptr;
     int rc = acquire_ws(ds, need, &base);
@@ -582,6 +594,7 @@ int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream) {
     out->leaf_elems = (int64_t)c.leaf_elems;
     out->search_probes = (int64_t)c.probes;
     out->searches = (int64_t)c.searches;
+    out->split_fallbacks = (int64_t)c.split_fallbacks;
     if (c.error) return fail(IM_ERR_DEVICE, "device error bits " + std::to_string(c.error));
     return IM_OK;
 }
@@ -629,6 +642,116 @@ int im_rotate(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t st
     if (lx == 0 || ly == 0) return IM_OK;
     if (!data) return fail(IM_ERR_INVALID_ARG, "null data pointer");
     IM_HIP(launch_rotate_single(data, lx, ly, elem_bytes, stream), "launch rotate");
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Method variants and comparators.
+// ---------------------------------------------------------------------------
+int inplace_merge_variant(void *data, int64_t L_A, int64_t L_B, int dtype, int split_method,
+                          int rot_method, hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (split_method != IM_SPLIT_CORANK && split_method != IM_SPLIT_FINDMEDIAN)
+        return fail(IM_ERR_INVALID_ARG, "unknown split method");
+    if (rot_method != IM_ROTATE_LS && rot_method != IM_ROTATE_CS)
+        return fail(IM_ERR_INVALID_ARG, "unknown exchange method");
+    if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
+    return run_pipeline(dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
+                        nullptr, stream, -1,
+                        split_method == IM_SPLIT_FINDMEDIAN ? kSplitFindMedian : kSplitCorank,
+                        rot_method == IM_ROTATE_CS ? kRotCS : kRotLS);
+}
+
+int im_divide(const void *data, int64_t L_A, int64_t L_B, int dtype, int method, int depth,
+              int64_t *d_sizes, hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (method != IM_SPLIT_CORANK && method != IM_SPLIT_FINDMEDIAN)
+        return fail(IM_ERR_INVALID_ARG, "unknown split method");
+    if (depth < 0 || depth > 24) return fail(IM_ERR_INVALID_ARG, "depth outside [0, 24]");
+    if (!d_sizes) return fail(IM_ERR_INVALID_ARG, "null output");
+    const int64_t leaves = (int64_t)1 << depth;
+    int64_t *buf = nullptr;
+    IM_HIP(hipMallocAsync((void **)&buf, sizeof(int64_t) * 8 * leaves, stream), "division buffers");
+    int64_t *nodes[2] = {buf, buf + 4 * leaves};
+    const int64_t root[4] = {0, L_A, 0, L_B};
+    hipError_t e = hipMemcpyAsync(nodes[0], root, sizeof(root), hipMemcpyHostToDevice, stream);
+    const int m = method == IM_SPLIT_FINDMEDIAN ? kSplitFindMedian : kSplitCorank;
+    for (int lv = 0; lv < depth && e == hipSuccess; ++lv)
+        e = launch_divide(dtype, data, L_A, L_B, m, lv, nodes[lv & 1], nodes[(lv + 1) & 1], stream);
+    // (a_off, la, b_off, lb) per pair -> (la, lb)
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(d_sizes, 2 * sizeof(int64_t), nodes[depth & 1] + 1,
+                             4 * sizeof(int64_t), sizeof(int64_t), leaves,
+                             hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(d_sizes + 1, 2 * sizeof(int64_t), nodes[depth & 1] + 3,
+                             4 * sizeof(int64_t), sizeof(int64_t), leaves,
+                             hipMemcpyDeviceToDevice, stream);
+    hipError_t ef = hipFreeAsync(buf, stream);
+    if (e != hipSuccess) return hip_fail(e, "division");
+    if (ef != hipSuccess) return hip_fail(ef, "division buffers");
+    return IM_OK;
+}
+
+int im_rotate_cs(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t stream) {
+    if (lx < 0 || ly < 0) return fail(IM_ERR_INVALID_ARG, "negative length");
+    if (elem_bytes != 4 && elem_bytes != 8) return fail(IM_ERR_UNSUPPORTED_DTYPE, "element size");
+    if (lx == 0 || ly == 0) return IM_OK;
+    if (!data) return fail(IM_ERR_INVALID_ARG, "null data pointer");
+    if (lx > (int64_t(1) << 46) || ly > (int64_t(1) << 46))
+        return fail(IM_ERR_INVALID_ARG, "length too large");
+    const int64_t lanes = cs_lanes(lx, ly);
+    void *stash = nullptr;
+    IM_HIP(hipMallocAsync(&stash, (size_t)elem_bytes * std::max<int64_t>(lanes, 1), stream),
+           "stash allocation");
+    hipError_t e = launch_rotate_cs_single(data, lx, ly, elem_bytes, stash, stream);
+    hipError_t ef = hipFreeAsync(stash, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch circular shifting");
+    if (ef != hipSuccess) return hip_fail(ef, "stash free");
+    return IM_OK;
+}
+
+int merge_out_of_place(const void *in, void *out, int64_t L_A, int64_t L_B, int dtype,
+                       hipStream_t stream) {
+    int rc = check_common(in, L_A, L_B, dtype);
+    if (rc) return rc;
+    const int64_t n = L_A + L_B;
+    if (n == 0) return IM_OK;
+    if (!out) return fail(IM_ERR_INVALID_ARG, "null output");
+    const char *ib = (const char *)in, *ob = (const char *)out;
+    const int64_t bytes = n * key_size(dtype);
+    if (ib < ob + bytes && ob < ib + bytes)
+        return fail(IM_ERR_INVALID_ARG, "input and output overlap");
+    const int64_t T = merge_oop_tile(key_size(dtype));
+    const int64_t nt = (n + T - 1) / T;
+    int64_t *buf = nullptr;
+    IM_HIP(hipMallocAsync((void **)&buf, sizeof(int64_t) * 2 * nt, stream), "tile buffers");
+    hipError_t e = launch_tile_diagonals(n, T, buf, stream);
+    if (e == hipSuccess)
+        e = launch_corank(dtype, in, L_A, L_B, buf, nt, buf + nt, nullptr, nullptr, stream);
+    if (e == hipSuccess) e = launch_merge_oop(dtype, in, out, L_A, L_B, buf + nt, stream);
+    hipError_t ef = hipFreeAsync(buf, stream);
+    if (e != hipSuccess) return hip_fail(e, "out-of-place merge");
+    if (ef != hipSuccess) return hip_fail(ef, "tile buffers");
+    return IM_OK;
+}
+
+int inplace_merge_buffered(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
+    const size_t bytes = (size_t)(L_A + L_B) * key_size(dtype);
+    void *tmp = nullptr;
+    IM_HIP(hipMallocAsync(&tmp, bytes, stream), "merge buffer allocation");
+    rc = merge_out_of_place(data, tmp, L_A, L_B, dtype, stream);
+    hipError_t e = rc == IM_OK ? hipMemcpyAsync(data, tmp, bytes, hipMemcpyDeviceToDevice, stream)
+                               : hipSuccess;
+    hipError_t ef = hipFreeAsync(tmp, stream);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "copy back");
+    if (ef != hipSuccess) return hip_fail(ef, "merge buffer free");
     return IM_OK;
 }
 

@@ -41,8 +41,9 @@ struct Node {
 // swap (a single linear-shifting step).  Otherwise three reversals.
 struct Rot {
     int64_t pos, lx, ly;
-    int64_t w0;   // first work item of this exchange in its level
-    int64_t nw;   // work items
+    int64_t w0;       // first work item of this exchange in its level
+    int64_t nw;       // work items
+    int64_t stash0;   // circular shifting: first stash slot (-1: none needed)
 };
 
 // A pair that is merged without further division.  Its tiles are processed
@@ -60,6 +61,7 @@ struct Counters {
     unsigned long long level_nodes[kMaxLevels + 1];  // nodes at each level
     unsigned long long level_rot[kMaxLevels];        // (count << 40) | work items
     unsigned long long level_rev[kMaxLevels];        // exchanges needing phase B
+    unsigned long long level_stash[kMaxLevels];      // circular shifting: stash slots used
     unsigned long long leaves;
     unsigned long long tiles;
     unsigned long long rotated;       // elements moved by exchanges
@@ -68,6 +70,7 @@ struct Counters {
     unsigned long long probes;        // key-pair probes of split searches
     unsigned long long searches;      // split searches
     unsigned long long levels_used;   // max level index that had nodes, +1
+    unsigned long long split_fallbacks;  // FindMedian splits replaced by co-rank splits
     unsigned int error;               // nonzero: a device-side check failed
     unsigned int pad;
 };
@@ -101,7 +104,21 @@ struct Plan {
     int64_t cap_nodes, cap_rot, cap_leaves, cap_tiles;
     uint32_t epoch;         // value a tile writes to its "inputs read" flag
     int32_t cfg;            // leaf-merge configuration (tile size per workgroup)
+    int32_t split_method;   // kSplitCorank or kSplitFindMedian
+    int32_t rot_method;     // kRotLS or kRotCS
+    int64_t cap_stash;      // circular shifting: stash slots per level
 };
+
+// Split of a division node: the exact co-rank (symmetric or middle diagonal),
+// or FindMedian (Sec. 3.3, Alg. 1) guarded by a validity and balance check.
+constexpr int kSplitCorank = 0;
+constexpr int kSplitFindMedian = 1;
+// Partition exchange: linear shifting (block swap / three reversals) or
+// circular shifting (cycles of Sec. 3.4).
+constexpr int kRotLS = 0;
+constexpr int kRotCS = 1;
+constexpr int kCsSeg = 256;      // cycle steps per lane in circular shifting
+constexpr int kCsLanes = 256;    // lanes per circular-shifting work item
 
 constexpr int kLeafCfgs = 4;   // leaf-merge tile configurations (im_leaf.hip)
 
@@ -117,6 +134,8 @@ struct Work {
     int32_t *tile_dep;       // per tile: [lo, hi] leaf-local tiles reading its window
     unsigned int *tile_flag; // per tile: == epoch once its inputs are in LDS
     int64_t *offsets1;       // [3] offsets of a single-instance call
+    void *cs_stash_k;        // circular shifting: first value of each cycle segment
+    void *cs_stash_v;        // ... and its payload
 };
 
 // Key-type dispatch codes (match im_dtype of the public header).
@@ -148,6 +167,20 @@ hipError_t launch_corank(int key, const void *data, int64_t la, int64_t lb, cons
                          int64_t nk, int64_t *d_out, const MlpDev *mlp, int32_t *d_probes,
                          hipStream_t s);
 hipError_t launch_rotate_single(void *data, int64_t lx, int64_t ly, int esize, hipStream_t s);
+// Circular-shifting exchange of one X|Y (stand-alone); stash: one element per
+// lane of cs_lanes(lx, ly), device memory.
+int64_t cs_lanes(int64_t lx, int64_t ly);
+hipError_t launch_rotate_cs_single(void *data, int64_t lx, int64_t ly, int esize, void *stash,
+                                   hipStream_t s);
+// Recursive division into 2^depth pairs without moving data (im_split.hip).
+hipError_t launch_divide(int key, const void *data, int64_t la, int64_t lb, int method,
+                         int level, const int64_t *nodes_in, int64_t *nodes_out, hipStream_t s);
+// Out-of-place merge of in[0,la) and in[la,la+lb) into out (im_leaf.hip):
+// d_rank[t] = co-rank of tile diagonal t*tile, t = 0..ntiles-1.
+int merge_oop_tile(int esize);
+hipError_t launch_tile_diagonals(int64_t n, int64_t tile, int64_t *d_k, hipStream_t s);
+hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int64_t lb,
+                            const int64_t *d_rank, hipStream_t s);
 hipError_t launch_check_sorted(int key, const void *data, const int64_t *d_offsets,
                                int64_t n_inst, Counters *ctr, hipStream_t s);
 

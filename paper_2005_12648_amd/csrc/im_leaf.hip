@@ -390,6 +390,97 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
     }
 }
 
+// ---- out-of-place merge (comparator) ---------------------------------------
+// The classic merge into a separate buffer: tile t of the output takes
+// in[ia_t, ia_{t+1}) and in[la + t*T - ia_t, ...) (co-ranks of the tile
+// diagonals), merged in LDS exactly like a leaf tile, and stored to out.
+// No flags and no waits: input and output do not overlap.  One workgroup per
+// tile.
+template <typename K, int THREADS, int IPT>
+__global__ __launch_bounds__(THREADS, 4) void k_merge_oop(const K *__restrict__ in,
+                                                          K *__restrict__ out, int64_t la,
+                                                          int64_t lb,
+                                                          const int64_t *__restrict__ rank,
+                                                          int64_t ntiles) {
+    using Ops = LeafOps<K, NoValL, THREADS, IPT>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    K *sk = reinterpret_cast<K *>(smem);
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int64_t S = la + lb;
+    const int64_t d0 = t * (int64_t)Ops::T;
+    const int64_t d1 = d0 + Ops::T < S ? d0 + Ops::T : S;
+    const int n = (int)(d1 - d0);
+    const int64_t ia0 = uniform64(rank[t]);
+    const int64_t ia1 = t + 1 < ntiles ? uniform64(rank[t + 1]) : la;
+    // clamp (only matters for unsorted input): keep both slices inside A, B
+    int64_t na = ia1 - ia0;
+    const int64_t na_lo = (d1 - lb - ia0) > 0 ? (d1 - lb - ia0) : 0;
+    const int64_t na_hi = (la - ia0) < (int64_t)n ? (la - ia0) : (int64_t)n;
+    if (na < na_lo) na = na_lo;
+    if (na > na_hi) na = na_hi;
+    TileGeo g;
+    g.out0 = d0;
+    g.a0 = ia0;
+    g.b0 = la + (d0 - ia0);
+    g.n = n;
+    g.na = (int)na;
+    g.tbase = 0;
+    g.ntiles = 1;
+    g.local = 0;
+    g.wlo = 0;
+    g.whi = 0;
+    stage_tile_dma<K, THREADS, IPT>(in, g, sk);
+    wait_dma();
+    __syncthreads();
+    K r[IPT];
+    NoValL v[1];
+    Ops::template merge<false>(g, sk, nullptr, r, v);
+    Ops::store(out, nullptr, g, r, v);
+}
+
+__global__ void k_tile_diagonals(int64_t n, int64_t tile, int64_t *d_k) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t * tile < n) d_k[t] = t * tile;
+}
+
+int merge_oop_tile(int esize) { return esize == 4 ? 512 * 35 : 512 * 17; }
+
+hipError_t launch_tile_diagonals(int64_t n, int64_t tile, int64_t *d_k, hipStream_t s) {
+    const int64_t nt = (n + tile - 1) / tile;
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_diagonals, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, n,
+                       tile, d_k);
+    return hipGetLastError();
+}
+
+template <typename K, int IPT>
+static hipError_t merge_oop_t(const void *in, void *out, int64_t la, int64_t lb,
+                              const int64_t *rank, hipStream_t s) {
+    constexpr int TH = 512;
+    const int64_t T = (int64_t)TH * IPT;
+    const int64_t nt = (la + lb + T - 1) / T;
+    if (nt <= 0) return hipSuccess;
+    const size_t lds = (size_t)(T + 2) * sizeof(K);
+    const void *fn = (const void *)&k_merge_oop<K, TH, IPT>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_merge_oop<K, TH, IPT>), dim3((unsigned)nt), dim3(TH), lds, s,
+                       (const K *)in, (K *)out, la, lb, rank, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int64_t lb,
+                            const int64_t *d_rank, hipStream_t s) {
+    switch (key) {
+        case kI32: return merge_oop_t<int32_t, 35>(in, out, la, lb, d_rank, s);
+        case kU32: return merge_oop_t<uint32_t, 35>(in, out, la, lb, d_rank, s);
+        case kI64: return merge_oop_t<int64_t, 17>(in, out, la, lb, d_rank, s);
+        case kU64: return merge_oop_t<uint64_t, 17>(in, out, la, lb, d_rank, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 // ---- leaf planning: tiles per leaf, exclusive scan, barrier counters ----
 constexpr int kPlanThreads = 1024;
 

@@ -212,6 +212,180 @@ __global__ __launch_bounds__(TH) void k_rotate_one(E *__restrict__ p, int64_t lx
     }
 }
 
+// ---------------------------------------------------------------------------
+// Circular shifting (Sec. 3.4, the comparator of linear shifting): element p
+// of X|Y (n = lx+ly) belongs at (p + ly) mod n.  The permutation has
+// gcd(n, ly) cycles of n/gcd steps; every element is read once and written
+// once, but a lane's successive accesses jump by ly.  Lane l of an exchange
+// takes cycle l mod g and segment l / g of kCsSeg steps; consecutive lanes
+// take consecutive cycles, so a wave's accesses are contiguous when there
+// are many cycles and scattered when there are few.  A cycle held by one lane
+// runs in phase 0; a cycle cut into segments needs the first value of every
+// segment saved before any lane writes (phase 0: stash, phase 1: walk).
+__device__ __forceinline__ int64_t cs_gcd(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// (a * b) mod n without overflow (n < 2^47): double and add.
+__device__ __forceinline__ int64_t cs_mulmod(int64_t a, int64_t b, int64_t n) {
+    int64_t r = 0;
+    a %= n;
+    while (b > 0) {
+        if (b & 1) {
+            r += a;
+            if (r >= n) r -= n;
+        }
+        a += a;
+        if (a >= n) a -= n;
+        b >>= 1;
+    }
+    return r;
+}
+
+// Walk `steps` steps of a cycle from position x (element values v carried):
+// reads run kCsBatch positions ahead of the writes (distinct positions of the
+// same cycle), so a batch of loads is in flight at once.
+constexpr int kCsBatch = 8;
+
+template <typename E>
+__device__ __forceinline__ void cs_walk(E *__restrict__ p, int64_t n, int64_t ly, int64_t x,
+                                        int64_t steps, E v, bool read_last) {
+    int64_t q = 0;
+    while (q < steps) {
+        int64_t pos[kCsBatch];
+        E nxt[kCsBatch];
+        const int64_t m = steps - q < kCsBatch ? steps - q : kCsBatch;
+#pragma unroll
+        for (int b = 0; b < kCsBatch; ++b) {
+            if (b < m) {
+                x += ly;
+                if (x >= n) x -= n;
+                pos[b] = x;
+                const bool last = q + b + 1 == steps;
+                if (!last || read_last) nxt[b] = p[x];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kCsBatch; ++b) {
+            if (b < m) {
+                p[pos[b]] = v;
+                v = nxt[b];
+            }
+        }
+        q += m;
+    }
+}
+
+// Lane `lane` of exchange R in phase `phase` (one array).
+template <typename E>
+__device__ __forceinline__ void cs_lane(E *__restrict__ base, const Rot &R, int64_t lane,
+                                        int phase, E *__restrict__ stash) {
+    const int64_t n = R.lx + R.ly;
+    const int64_t g = cs_gcd(n, R.ly);
+    const int64_t L = n / g;
+    const int64_t nseg = (L + kCsSeg - 1) / kCsSeg;
+    if (lane >= g * nseg) return;
+    E *p = base + R.pos;
+    const int64_t c = lane % g, sg = lane / g;
+    if (nseg == 1) {
+        // the whole cycle: its start is read first and written last
+        if (phase != 0) return;
+        cs_walk<E>(p, n, R.ly, c, L, p[c], false);
+        return;
+    }
+    const int64_t q0 = sg * kCsSeg;
+    const int64_t q1 = q0 + kCsSeg < L ? q0 + kCsSeg : L;
+    int64_t x0 = c + cs_mulmod(q0, R.ly, n);
+    if (x0 >= n) x0 -= n;
+    if (phase == 0) {
+        stash[R.stash0 + lane] = p[x0];
+    } else {
+        // writes reach the next segment's start, whose value is in the stash
+        cs_walk<E>(p, n, R.ly, x0, q1 - q0, stash[R.stash0 + lane], false);
+    }
+}
+
+template <typename EK, typename EV>
+__global__ __launch_bounds__(kCsLanes) void k_rotate_cs(EK *__restrict__ keys, EV *__restrict__ vals,
+                                                        const Rot *__restrict__ rot,
+                                                        const Counters *__restrict__ ctr,
+                                                        int64_t cap_rot, int level, int phase,
+                                                        EK *__restrict__ sk, EV *__restrict__ sv) {
+    const unsigned long long packed = ctr->level_rot[level];
+    int64_t nrot = (int64_t)(packed >> kRotCountShift);
+    if (nrot > cap_rot) nrot = cap_rot;
+    const int64_t nitems = (int64_t)(packed & kRotWorkMask);
+    for (int64_t wi = blockIdx.x; wi < nitems; wi += gridDim.x) {
+        int64_t lo = 0, hi = nrot;
+        while (hi - lo > 1) {
+            int64_t mid = (lo + hi) >> 1;
+            if (rot[mid].w0 <= wi) lo = mid; else hi = mid;
+        }
+        if (nrot == 0) break;
+        const Rot R = rot[lo];
+        if (wi < R.w0 || wi >= R.w0 + R.nw) continue;   // a dropped exchange
+        const int64_t lane = (wi - R.w0) * kCsLanes + threadIdx.x;
+        cs_lane<EK>(keys, R, lane, phase, sk);
+        if constexpr (!std::is_same<EV, NoVal>::value) cs_lane<EV>(vals, R, lane, phase, sv);
+    }
+}
+
+template <typename E>
+__global__ __launch_bounds__(kCsLanes) void k_rotate_cs_one(E *__restrict__ p, Rot R, int phase,
+                                                            E *__restrict__ stash) {
+    for (int64_t wi = blockIdx.x; wi < R.nw; wi += gridDim.x)
+        cs_lane<E>(p, R, wi * kCsLanes + threadIdx.x, phase, stash);
+}
+
+template <typename EK, typename EV>
+static hipError_t rot_cs_t(void *keys, void *vals, const Plan &pl, const Work &w, int level,
+                           int phase, hipStream_t s) {
+    hipLaunchKernelGGL((k_rotate_cs<EK, EV>), dim3(2048), dim3(kCsLanes), 0, s, (EK *)keys,
+                       (EV *)vals, w.rot, w.ctr, pl.cap_rot, level, phase, (EK *)w.cs_stash_k,
+                       (EV *)w.cs_stash_v);
+    return hipGetLastError();
+}
+
+int64_t cs_lanes(int64_t lx, int64_t ly) {
+    int64_t n = lx + ly, a = n, b = ly;
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    const int64_t L = n / a;
+    return a * ((L + kCsSeg - 1) / kCsSeg);
+}
+
+hipError_t launch_rotate_cs_single(void *data, int64_t lx, int64_t ly, int esize, void *stash,
+                                   hipStream_t s) {
+    if (lx <= 0 || ly <= 0) return hipSuccess;
+    Rot R;
+    R.pos = 0; R.lx = lx; R.ly = ly; R.w0 = 0;
+    const int64_t lanes = cs_lanes(lx, ly);
+    R.nw = (lanes + kCsLanes - 1) / kCsLanes;
+    R.stash0 = 0;
+    const int g = (int)(R.nw < 2048 ? R.nw : 2048);
+    for (int ph = 0; ph < 2; ++ph) {
+        if (esize == 4)
+            hipLaunchKernelGGL(k_rotate_cs_one<uint32_t>, dim3(g), dim3(kCsLanes), 0, s,
+                               (uint32_t *)data, R, ph, (uint32_t *)stash);
+        else if (esize == 8)
+            hipLaunchKernelGGL(k_rotate_cs_one<uint64_t>, dim3(g), dim3(kCsLanes), 0, s,
+                               (uint64_t *)data, R, ph, (uint64_t *)stash);
+        else
+            return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename EK, typename EV>
 static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, int level,
                         int phase, hipStream_t s) {
@@ -224,6 +398,18 @@ static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, i
 
 hipError_t launch_rotate(int esize_k, int esize_v, void *keys, void *vals, const Plan &pl,
                          const Work &w, int level, int phase, hipStream_t s) {
+    if (pl.rot_method == kRotCS) {
+        if (esize_k == 4) {
+            if (esize_v == 0) return rot_cs_t<uint32_t, NoVal>(keys, vals, pl, w, level, phase, s);
+            if (esize_v == 4) return rot_cs_t<uint32_t, uint32_t>(keys, vals, pl, w, level, phase, s);
+            if (esize_v == 8) return rot_cs_t<uint32_t, uint64_t>(keys, vals, pl, w, level, phase, s);
+        } else if (esize_k == 8) {
+            if (esize_v == 0) return rot_cs_t<uint64_t, NoVal>(keys, vals, pl, w, level, phase, s);
+            if (esize_v == 4) return rot_cs_t<uint64_t, uint32_t>(keys, vals, pl, w, level, phase, s);
+            if (esize_v == 8) return rot_cs_t<uint64_t, uint64_t>(keys, vals, pl, w, level, phase, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if (esize_k == 4) {
         if (esize_v == 0) return rot_t<uint32_t, NoVal>(keys, vals, pl, w, level, phase, s);
         if (esize_v == 4) return rot_t<uint32_t, uint32_t>(keys, vals, pl, w, level, phase, s);

@@ -39,6 +39,45 @@ __device__ __forceinline__ int64_t corank_plain(const K *__restrict__ A, int64_t
     return corank_binary(A, la, B, lb, k, lo, hi, probes);
 }
 
+// FindMedian (Sec. 3.3, Alg. 1): a double binary search for a pivot pair
+// (p_A, p_B) with A[0,p_A) <= B[p_B,..) and B[0,p_B) <= A[p_A,..) that keeps
+// |A0|+|B0| close to |A1|+|B1|, in O(log L_A + log L_B) probes.  The probes
+// start at the middles of A and B; when the loop stops because the probed
+// values are equal, that probe pair is the result (the printed listing tests
+// p_A, p_B before setting them and recomputes midpoints after such a stop).
+// One lane, sequential dependent probes.  `probes` counts value pairs read.
+template <typename K>
+__device__ __forceinline__ void find_median(const K *__restrict__ A, int64_t la,
+                                            const K *__restrict__ B, int64_t lb, int64_t &pa,
+                                            int64_t &pb, uint32_t &probes) {
+    if (la == 0 || lb == 0 || A[la - 1] <= B[0]) { pa = la; pb = 0; return; }
+    if (!(A[0] <= B[lb - 1])) { pa = 0; pb = lb; return; }
+    int64_t left_a = 0, limit_a = la, left_b = 0, limit_b = lb;
+    pa = la / 2;
+    pb = lb / 2;
+    K va = A[pa], vb = B[pb];
+    ++probes;
+    while (left_a < limit_a && left_b < limit_b && va != vb) {
+        pa = (limit_a - left_a) / 2 + left_a;
+        pb = (limit_b - left_b) / 2 + left_b;
+        va = A[pa];
+        vb = B[pb];
+        ++probes;
+        const int64_t lo = pa + pb, hi = (la - pa) + (lb - pb);
+        if (va < vb) {
+            if (lo < hi) left_a = pa + 1;
+            else limit_b = pb;
+        } else {
+            if (lo < hi) left_b = pb + 1;
+            else limit_a = pa;
+        }
+        // the loop test reads the values at the current probe pair
+    }
+    if (left_a < limit_a && left_b < limit_b) return;   // stopped on an equal probe
+    pa = (limit_a - left_a) / 2 + left_a;
+    pb = (limit_b - left_b) / 2 + left_b;
+}
+
 // fp32 forward pass of the 1 -> H -> 1 ReLU network.
 __device__ __forceinline__ float mlp_eval(const MlpDev *__restrict__ M, float x) {
     float y = M->p[3 * kMlpHidden];

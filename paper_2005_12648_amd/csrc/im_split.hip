@@ -61,10 +61,43 @@ __global__ void k_init(Counters *ctr, Node *nodes0, const int64_t *__restrict__ 
     }
 }
 
+__device__ __forceinline__ int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Circular shifting of X|Y (n = lx+ly): gcd(n, ly) cycles of n/gcd steps,
+// each cut into segments of kCsSeg steps, one lane per (cycle, segment).
+__device__ __forceinline__ void cs_shape(int64_t lx, int64_t ly, int64_t &g, int64_t &nseg) {
+    const int64_t n = lx + ly;
+    g = gcd64(n, ly);
+    const int64_t L = n / g;
+    nseg = (L + kCsSeg - 1) / kCsSeg;
+}
+
 __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int level, int64_t pos,
                                          int64_t lx, int64_t ly) {
-    int64_t nw;
-    if (lx == ly) {
+    int64_t nw, stash0 = -1;
+    if (pl.rot_method == kRotCS) {
+        int64_t g, nseg;
+        cs_shape(lx, ly, g, nseg);
+        nw = (g * nseg + kCsLanes - 1) / kCsLanes;
+        if (nseg > 1) {
+            // cycles cut into several segments keep the first value of every
+            // segment in the level's stash (fewer than 2*(lx+ly)/kCsSeg slots)
+            const unsigned long long st =
+                atomicAdd(&w.ctr->level_stash[level], (unsigned long long)(g * nseg));
+            if ((int64_t)st + g * nseg > pl.cap_stash) {
+                atomicOr(&w.ctr->error, kErrCapacity);
+                return;
+            }
+            stash0 = (int64_t)st;
+        }
+    } else if (lx == ly) {
         nw = (lx + kRotChunk - 1) / kRotChunk;
     } else {
         int64_t a = (lx / 2 + kRotChunk - 1) / kRotChunk + (ly / 2 + kRotChunk - 1) / kRotChunk;
@@ -82,9 +115,10 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
     r.pos = pos; r.lx = lx; r.ly = ly;
     r.w0 = (int64_t)(packed & kRotWorkMask);
     r.nw = nw;
+    r.stash0 = stash0;
     w.rot[slot] = r;
     atomicAdd(&w.ctr->rotated, (unsigned long long)(lx + ly));
-    if (lx != ly) {
+    if (lx != ly && pl.rot_method != kRotCS) {
         atomicAdd(&w.ctr->rotated_rev, (unsigned long long)(lx + ly));
         atomicAdd(&w.ctr->level_rev[level], 1ull);
     }
@@ -106,6 +140,27 @@ __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const N
     w.leaves[slot] = lf;
 }
 
+// Split node nd at (i, j): Alg. 3's "shift" exchanges A[i, la) and B[0, j),
+// which turns A_0 A_1 B_0 B_1 into A_0 B_0 A_1 B_1, and both pairs go to the
+// next level.
+__device__ __forceinline__ void emit_split(const Plan &pl, const Work &w, int level, Node *out,
+                                           const Node &nd, int64_t i, int64_t j) {
+    const int64_t la = nd.la, lb = nd.lb, kk = i + j;
+    if (la - i > 0 && j > 0) emit_rot(pl, w, level, nd.base + i, la - i, j);
+    unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level + 1], 2ull);
+    if ((int64_t)slot + 1 >= pl.cap_nodes) {
+        atomicOr(&w.ctr->error, kErrCapacity);
+        return;
+    }
+    Node l, r;
+    l.base = nd.base; l.la = i; l.lb = j; l.k0 = nd.k0; l.i0 = nd.i0; l.inst = nd.inst;
+    l.pad = 0;
+    r.base = nd.base + kk; r.la = la - i; r.lb = lb - j; r.k0 = nd.k0 + kk;
+    r.i0 = nd.i0 + i; r.inst = nd.inst; r.pad = 0;
+    out[slot] = l;
+    out[slot + 1] = r;
+}
+
 // One lane per node classifies it (early exits, leaf); the nodes of a wave
 // that must be split are then searched one after another by the whole wave
 // with the cooperative 64-ary co-rank (a handful of dependent rounds).
@@ -122,7 +177,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (gid == 0 && cnt > 0) atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
-    uint32_t rounds = 0, searches = 0;
+    uint32_t rounds = 0, searches = 0;          // wave-uniform counts
+    uint32_t fm_probes = 0, fm_searches = 0;    // per lane (FindMedian)
     for (int64_t idx0 = gid - lane; idx0 < cnt; idx0 += stride) {   // wave-uniform
         const int64_t idx = idx0 + lane;
         Node nd;
@@ -148,6 +204,25 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
                 const int64_t mx = la > lb ? la : lb;
                 k = (mx * 16 <= S * 9) ? la : S / 2;
                 split = true;
+                if (pl.split_method == kSplitFindMedian) {
+                    // FindMedian, kept when its split is valid and no child
+                    // exceeds the 9/16 bound the level count assumes; else
+                    // the exact co-rank split below
+                    int64_t pa, pb;
+                    find_median(A, la, B, lb, pa, pb, fm_probes);
+                    ++fm_searches;
+                    const int64_t kf = pa + pb;
+                    const int64_t big = kf > S - kf ? kf : S - kf;
+                    const bool valid =
+                        (pa == 0 || pb == lb || A[pa - 1] <= B[pb]) &&
+                        (pb == 0 || pa == la || B[pb - 1] <= A[pa]);
+                    if (valid && big * 16 <= S * 9 + 16 && kf > 0 && kf < S) {
+                        emit_split(pl, w, level, out, nd, pa, pb);
+                        split = false;
+                    } else {
+                        atomicAdd(&w.ctr->split_fallbacks, 1ull);
+                    }
+                }
             }
         }
         unsigned long long todo = __ballot(split);
@@ -174,27 +249,72 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
                 i = corank_group<64>(A, la, B, lb, kk, rounds);
             }
             if (lane != src) continue;
-            const int64_t j = kk - i;
-            // Alg. 3 "shift": exchange A[i, la) and B[0, j) -> ... A_0 B_0 A_1 B_1
-            if (la - i > 0 && j > 0) emit_rot(pl, w, level, base + i, la - i, j);
-            unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level + 1], 2ull);
-            if ((int64_t)slot + 1 >= pl.cap_nodes) {
-                atomicOr(&w.ctr->error, kErrCapacity);
-                continue;
-            }
-            Node l, r;
-            l.base = base; l.la = i; l.lb = j; l.k0 = nd.k0; l.i0 = nd.i0; l.inst = nd.inst;
-            l.pad = 0;
-            r.base = base + kk; r.la = la - i; r.lb = lb - j; r.k0 = nd.k0 + kk;
-            r.i0 = nd.i0 + i; r.inst = nd.inst; r.pad = 0;
-            out[slot] = l;
-            out[slot + 1] = r;
+            emit_split(pl, w, level, out, nd, i, kk - i);
         }
+    }
+    if (pl.split_method == kSplitFindMedian) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            fm_probes += __shfl_xor(fm_probes, o, 64);
+            fm_searches += __shfl_xor(fm_searches, o, 64);
+        }
+        searches += fm_searches;
+        rounds += fm_probes;
     }
     if (lane == 0 && searches) {
         atomicAdd(&w.ctr->searches, (unsigned long long)searches);
         atomicAdd(&w.ctr->probes, (unsigned long long)rounds);
     }
+}
+
+// Recursive division without data movement (the pivot search of every
+// level of Sec. 3, as sOptMov does before it moves anything): node q of level
+// `level` is (a_off, la, b_off, lb) in the original A and B; its children are
+// 2q and 2q+1 of the next level.  One lane per node.
+template <typename K>
+__global__ __launch_bounds__(kSplitThreads) void k_divide(const K *__restrict__ A,
+                                                          const K *__restrict__ B, int method,
+                                                          int64_t nnodes,
+                                                          const int64_t *__restrict__ in,
+                                                          int64_t *__restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnodes) return;
+    const int64_t ao = in[4 * q], la = in[4 * q + 1], bo = in[4 * q + 2], lb = in[4 * q + 3];
+    int64_t i, j;
+    uint32_t probes = 0;
+    if (method == kSplitFindMedian) {
+        find_median(A + ao, la, B + bo, lb, i, j, probes);
+    } else {
+        const int64_t k = (la + lb) / 2;
+        i = corank_plain(A + ao, la, B + bo, lb, k, probes);
+        j = k - i;
+    }
+    int64_t *c = out + 8 * q;
+    c[0] = ao; c[1] = i; c[2] = bo; c[3] = j;
+    c[4] = ao + i; c[5] = la - i; c[6] = bo + j; c[7] = lb - j;
+}
+
+template <typename K>
+static hipError_t divide_t(const void *data, int64_t la, int method, int level,
+                           const int64_t *in, int64_t *out, hipStream_t s) {
+    const int64_t nn = (int64_t)1 << level;
+    const int g = (int)((nn + kSplitThreads - 1) / kSplitThreads);
+    const K *A = (const K *)data;
+    hipLaunchKernelGGL(k_divide<K>, dim3(g), dim3(kSplitThreads), 0, s, A, A + la, method, nn,
+                       in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_divide(int key, const void *data, int64_t la, int64_t lb, int method,
+                         int level, const int64_t *nodes_in, int64_t *nodes_out, hipStream_t s) {
+    (void)lb;
+    switch (key) {
+        case kI32: return divide_t<int32_t>(data, la, method, level, nodes_in, nodes_out, s);
+        case kU32: return divide_t<uint32_t>(data, la, method, level, nodes_in, nodes_out, s);
+        case kI64: return divide_t<int64_t>(data, la, method, level, nodes_in, nodes_out, s);
+        case kU64: return divide_t<uint64_t>(data, la, method, level, nodes_in, nodes_out, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // Tile co-ranks: tile t of leaf l starts at local diagonal (t - tile_start[l]) * tile.

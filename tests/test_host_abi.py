@@ -80,6 +80,19 @@ def test_validation_codes_without_device_work():
     assert lib.inplace_merge_autotune(fake, fake, 4, 100, 0, 0, 7, 3, None, None, None) == -2
     assert lib.inplace_merge_autotune(fake, fake, 4, 100, 0, 0, -1, 0, None, None, None) == -1
     assert lib.inplace_merge_autotune(None, fake, 4, 100, 0, 0, -1, 3, None, None, None) == -1
+    # method variants and comparators
+    assert lib.inplace_merge_variant(fake, 4, 4, 0, 2, 0, None) == -1
+    assert lib.inplace_merge_variant(fake, 4, 4, 0, 0, 5, None) == -1
+    assert lib.inplace_merge_variant(fake, 4, 4, 7, 0, 0, None) == -2
+    assert lib.im_divide(fake, 4, 4, 0, 3, 2, fake, None) == -1
+    assert lib.im_divide(fake, 4, 4, 0, 0, 25, fake, None) == -1
+    assert lib.im_divide(fake, 4, 4, 0, 0, 2, None, None) == -1
+    assert lib.im_rotate_cs(fake, 3, 4, 2, None) == -2
+    assert lib.im_rotate_cs(fake, 0, 4, 4, None) == 0
+    assert lib.merge_out_of_place(fake, fake, 4, 4, 0, None) == -1     # overlap
+    assert lib.merge_out_of_place(fake, None, 4, 4, 0, None) == -1
+    assert lib.inplace_merge_buffered(fake, -1, 4, 0, None) == -1
+    assert lib.inplace_merge_buffered(fake, 0, 4, 0, None) == 0
     # empty work is a successful no-op that touches nothing
     assert lib.inplace_merge(None, 0, 0, 0, None) == 0
     assert lib.inplace_merge(fake, 0, 7, 0, None) == 0
