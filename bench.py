@@ -166,21 +166,40 @@ def bench_headline(torch, im, oracle, gen, dev, args):
     off1 = torch.tensor([0, la, n], dtype=torch.int64, device=dev)
     chosen, tune_ms = im.autotune(pristine, off1, reps=3)
     log("c2: autotune ms per config", ["%.3f" % m for m in tune_ms], "chosen", chosen)
-    ms, prof, bufs = timed_merges(torch, im, pristine, la, args.steps, args.warmup, profile=True)
-    stats = im.fetch_stats()
+    # the timed steps carry no stage events; a second pass with per-stage
+    # events (which add small gaps between launches) feeds the roofline
+    ms, _, bufs = timed_merges(torch, im, pristine, la, args.steps, args.warmup)
     log("c2: %.3f ms/step, %.1f Gelem/s" % (ms, n / ms / 1e6))
+    ms_prof, prof, pbufs = timed_merges(torch, im, pristine, la, args.steps, 0, profile=True)
+    stats = im.fetch_stats()
+    del pbufs
+    log("c2: profiled pass %.3f ms/step" % ms_prof)
     res = {"ms": ms, "prof": prof, "stats": stats, "n": n,
            "tune_ms": [round(m, 4) for m in tune_ms]}
     cpu = None
     if not args.no_cpu:
         host = pristine.cpu().numpy()
-        log("c2: CPU oracle (single thread) for %.0f s" % args.cpu_seconds)
-        want, med_s, reps = cpu_oracle_time(lambda: oracle.merge(host, la), args.cpu_seconds)
-        cpu = {"value": round(n / med_s / 1e9, 4), "unit": "Gelem/s", "cores": 1,
-               "kind": "oracle",
-               "sample": "full workload (int32 2^27+2^27), %d repetitions, median; "
-                         "stable two-finger merge into a fresh buffer + copy back" % reps,
+        half = args.cpu_seconds / 2
+        log("c2: CPU oracle, single thread then all host cores, %.0f s each" % half)
+        want, med_s, reps = cpu_oracle_time(lambda: oracle.merge(host, la), half)
+        par_out = {}
+
+        def run_par():
+            r, th = oracle.merge_par(host, la)
+            par_out["threads"] = th
+            return r
+        want_p, med_p, reps_p = cpu_oracle_time(run_par, half)
+        cpu = {"value": round(n / med_p / 1e9, 4), "unit": "Gelem/s",
+               "cores": par_out["threads"], "kind": "oracle",
+               "sample": "full workload (int32 2^27+2^27), %d repetitions, median; the "
+                         "oracle's all-cores stable merge (OpenMP: cuts at equal ranks, "
+                         "pieces merged into a fresh buffer, copied back)" % reps_p,
+               "single_thread_value": round(n / med_s / 1e9, 4),
+               "single_thread_sample": "%d repetitions, median; two-finger merge into a "
+                                       "fresh buffer + copy back" % reps,
                "host_cores_available": os.cpu_count()}
+        if not np.array_equal(want, want_p):
+            raise SystemExit("oracle all-cores merge differs from the single-thread merge")
         res["mismatch"] = mismatches(bufs[0], want) + mismatches(bufs[-1], want)
         log("c2: mismatches vs oracle:", res["mismatch"])
     res["cpu"] = cpu
@@ -344,6 +363,116 @@ def bench_learned(torch, im, oracle, gen, dev, steps):
             "train_s": round(train_s, 3), "mismatches_learned": bad_l, "mismatches_plain": bad_p}
 
 
+def bench_findmedian(torch, im, gen, dev, steps):
+    """FindMedian (Alg. 1) against the exact co-rank split: the paper's
+    imbalance study on its W1 generator (largest pair with FindMedian over
+    largest pair with exact middle splits, minus one), and the whole merge
+    of the balanced int32 workload with either split."""
+    study = {}
+    for logs in (16, 20, 22):
+        S = 2 ** logs
+        for frac in (0.25, 0.5, 0.75):
+            data = gen.paper_w1_pair(S, frac, SEED + 60 + logs)
+            la = int(S * frac)
+            t = torch.from_numpy(data).to(dev)
+            a, b = data[:la], data[la:]
+            row_pair, row_work = {}, {}
+            for depth in range(1, 17):
+                if 2 ** depth > S // 4:
+                    break
+                mx = {}
+                for name, m in (("fm", im.SPLIT_FINDMEDIAN), ("ex", im.SPLIT_CORANK)):
+                    sz = im.divide(t, la, depth, m).cpu().numpy()
+                    ao = np.concatenate([[0], np.cumsum(sz[:, 0])])[:-1]
+                    bo = np.concatenate([[0], np.cumsum(sz[:, 1])])[:-1]
+                    tot = sz.sum(axis=1)
+                    # a pair needs a merge when both parts are non-empty and
+                    # its last A element exceeds its first B element
+                    need = (sz[:, 0] > 0) & (sz[:, 1] > 0)
+                    idx = np.flatnonzero(need)
+                    need[idx] = a[ao[idx] + sz[idx, 0] - 1] > b[np.minimum(bo[idx], b.size - 1)]
+                    mx[name] = (int(tot.max()), int((tot * need).max()))
+                T = str(2 ** depth)
+                row_pair[T] = round((mx["fm"][0] - mx["ex"][0]) / mx["ex"][0], 5)
+                row_work[T] = (round((mx["fm"][1] - mx["ex"][1]) / mx["ex"][1], 5)
+                               if mx["ex"][1] else None)
+            key = "S=2^%d split=%.2f" % (logs, frac)
+            study[key] = {"largest_pair": row_pair, "largest_pair_needing_a_merge": row_work}
+    la = lb = 2 ** 27
+    n = la + lb
+    pristine = gen.torch_pair_uniform(la, lb, SEED + 20, dev)
+    res = {}
+    for name, split in (("corank", im.SPLIT_CORANK), ("findmedian", im.SPLIT_FINDMEDIAN)):
+        ms, _, bufs = timed_merges(torch, im, pristine, la, steps, 1,
+                                   fn=lambda b: im.inplace_merge_variant(b, la, split,
+                                                                         im.ROTATE_LS))
+        st = im.fetch_stats()
+        res[name] = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
+                     "levels_used": st["levels_used"], "leaves": st["leaves"],
+                     "split_fallbacks": st["split_fallbacks"]}
+        del bufs
+    same = True
+    a = pristine.clone()
+    b = pristine.clone()
+    im.inplace_merge_variant(a, la, im.SPLIT_FINDMEDIAN, im.ROTATE_LS)
+    im.inplace_merge(b, la)
+    same = bool(torch.equal(a, b))
+    log("f2: findmedian merge %.3f ms, corank %.3f ms" % (res["findmedian"]["ms"],
+                                                         res["corank"]["ms"]))
+    return {"workload": "W1 generator (Sec. 4) at S=2^16..2^22, splits 1/4,1/2,3/4; merge of "
+                        "int32 2^27+2^27",
+            "imbalance_rel": study,
+            "imbalance_note": "(max FindMedian - max exact co-rank) / max exact co-rank, over "
+                              "the 2^depth pairs; 'largest_pair' counts every pair, "
+                              "'largest_pair_needing_a_merge' only pairs with both parts "
+                              "non-empty and out of order",
+            "merge_c2": res, "findmedian_equals_corank_result": same}
+
+
+def bench_exchanges(torch, im, oracle, gen, dev, steps):
+    """Linear vs circular shifting (Sec. 3.4), alone and inside the merge, and
+    the out-of-place comparators."""
+    out = {}
+    n = 2 ** 28
+    x = torch.arange(n, dtype=torch.int32, device=dev)
+    for label, lx in (("swap 2^27|2^27", n // 2), ("2^27+3|2^27-3", n // 2 + 3),
+                      ("2^24|rest", 2 ** 24)):
+        buf = x.clone()
+        ms_ls = event_timed(torch, x, buf, lambda: im.rotate(buf, lx), max(steps, 3))
+        ms_cs = event_timed(torch, x, buf, lambda: im.rotate_cs(buf, lx), max(steps, 3))
+        moved = 2 * 4 * n          # every element read and written once (definition)
+        out[label] = {"ls_ms": round(ms_ls, 4), "cs_ms": round(ms_cs, 4),
+                      "ls_eff_gb_s": round(moved / ms_ls / 1e6, 1),
+                      "cs_eff_gb_s": round(moved / ms_cs / 1e6, 1)}
+        del buf
+    del x
+    torch.cuda.empty_cache()
+    la = lb = 2 ** 27
+    pristine = gen.torch_pair_uniform(la, lb, SEED + 20, dev)
+    merges = {}
+    for name, fn in (
+            ("in_place_ls", lambda b: im.inplace_merge(b, la)),
+            ("in_place_cs", lambda b: im.inplace_merge_variant(b, la, im.SPLIT_CORANK,
+                                                               im.ROTATE_CS)),
+            ("buffered_alloc_merge_copy_free", lambda b: im.inplace_merge_buffered(b, la))):
+        ms, _, bufs = timed_merges(torch, im, pristine, la, 3, 1, fn=fn)
+        merges[name] = {"ms": round(ms, 4), "gelem_s": round((la + lb) / ms / 1e6, 2)}
+        del bufs
+    o = torch.empty_like(pristine)
+    ms_oop = event_timed(torch, pristine, pristine.clone(),
+                         lambda: im.merge_out_of_place(pristine, la, o), 3)
+    merges["out_of_place_only"] = {"ms": round(ms_oop, 4),
+                                   "gelem_s": round((la + lb) / ms_oop / 1e6, 2)}
+    want = im.merge_out_of_place(pristine, la)
+    chk = pristine.clone()
+    im.inplace_merge_variant(chk, la, im.SPLIT_CORANK, im.ROTATE_CS)
+    merges["cs_equals_out_of_place"] = bool(torch.equal(chk, want))
+    log("f3: exchanges", out)
+    log("f3: merges", merges)
+    return {"workload": "int32 exchanges of 2^28 elements; merges of int32 2^27+2^27",
+            "exchange": out, "merge_c2": merges}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,6 +514,10 @@ def main():
         forms["c4_sort"] = bench_sort(torch, im, oracle, gen, dev)
         torch.cuda.empty_cache()
         forms["c5_learned"] = bench_learned(torch, im, oracle, gen, dev, args.steps)
+        torch.cuda.empty_cache()
+        forms["f2_findmedian"] = bench_findmedian(torch, im, gen, dev, 3)
+        torch.cuda.empty_cache()
+        forms["f3_exchange_and_out_of_place"] = bench_exchanges(torch, im, oracle, gen, dev, 3)
     st = head["stats"]
     line = {
         "metric": "Gelem/s, in-place merge of int32 L_A=L_B=2^27",

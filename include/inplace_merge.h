@@ -225,7 +225,7 @@ int merge_out_of_place(const void *in, void *out, int64_t L_A, int64_t L_B, int 
                        hipStream_t stream);
 int inplace_merge_buffered(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream);
 
-/* In-place merge sort of data[0, n): each tile is sorted in LDS, then/* In-place merge sort of data[0, n): each tile is sorted in LDS, then
+/* In-place merge sort of data[0, n): each tile is sorted in LDS, then
  * bottom-up passes of the batched merge double the sorted run length; the
  * unpaired last run of a pass is carried over unchanged. */
 int inplace_merge_sort(void *data, int64_t n, int dtype, hipStream_t stream);

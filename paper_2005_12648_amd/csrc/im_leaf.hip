@@ -32,6 +32,7 @@
 // slots [s, s+3G) are therefore all read without any wait, the readers of
 // s's window are among them, and s is stored.  The wait is bounded: on
 // expiry the workgroup raises an error bit and skips its store.
+#include <limits>
 #include <type_traits>
 #include "im_common.h"
 
@@ -41,8 +42,15 @@ struct NoValL {};
 
 constexpr unsigned kSpinLimit = 1u << 26;
 
-template <int T>
-struct LdsPad { static constexpr int elems = T + 2; };   // + look-ahead slack
+// LDS slots of a tile: T inputs, the B sentinel and the reads of the last
+// thread's steps past the end (their outputs are discarded).
+template <int T, int IPT>
+struct LdsPad { static constexpr int elems = T + IPT + 2; };
+
+template <typename K>
+__device__ __forceinline__ K key_max() {
+    return std::numeric_limits<K>::max();
+}
 
 // Geometry of one tile: output window [out0, out0+n), A-slice (na elements
 // from a0) and B-slice (n - na elements from b0), all as element indices of
@@ -163,7 +171,7 @@ template <typename K, typename V, int THREADS, int IPT>
 struct LeafOps {
     static constexpr int T = THREADS * IPT;
     static constexpr bool HAS_V = !std::is_same<V, NoValL>::value;
-    static constexpr int PE = LdsPad<T>::elems;
+    static constexpr int PE = LdsPad<T, IPT>::elems;
     static constexpr int VN = HAS_V ? IPT : 1;
 
     // Load the tile's slices into LDS and publish "inputs read".
@@ -172,6 +180,7 @@ struct LeafOps {
         stage_tile_dma<K, THREADS, IPT>(keys, g, sk);
         if constexpr (HAS_V) stage_tile_dma<V, THREADS, IPT>(vals, g, sv);
         wait_dma();
+        if (threadIdx.x == 0) sk[g.n] = key_max<K>();   // B sentinel
         __syncthreads();
         if (g.ntiles > 1 && threadIdx.x == 0)
             __hip_atomic_store(&w.tile_flag[g.tbase + g.local], pl.epoch, __ATOMIC_RELAXED,
@@ -196,26 +205,29 @@ struct LeafOps {
                 if (sk[mid] <= sk[na + d - 1 - mid]) lo = mid + 1;
                 else hi = mid;
             }
-            int ia = lo, ib = d - lo;
-            // sk has PE > n entries, so the look-ahead reads stay inside LDS.
+            // ia: next A index, bi: LDS index of the next B element.  A
+            // sentinel (the key type's maximum) follows B, so an exhausted B
+            // never wins (a <= max, and ties take A anyway); an exhausted A
+            // is tested by index.  Steps past the tile end (last thread) read
+            // the padding and their outputs are not stored.
+            int ia = lo, bi = na + (d - lo);
             K a = sk[ia];
-            K b = sk[na + ib];
+            K b = sk[bi];
             // branch-free steps (selects only): no per-step exec masks
 #pragma unroll
             for (int e = 0; e < IPT; ++e) {
-                const bool ta = (ib >= nb) || (ia < na && a <= b);
+                const bool ta = (ia < na) && (a <= b);
                 K o = ta ? a : b;
                 // With two register sets live (depth 3), materialise the
                 // output now: otherwise the select is sunk to its use and
                 // both candidates plus the mask stay live, which spills.
                 if constexpr (MATERIALISE) asm volatile("" : "+v"(o));
                 out[e] = o;
-                const int src = ta ? ia : na + ib;
-                if constexpr (HAS_V) vout[e] = sv[src > PE - 1 ? PE - 1 : src];
-                const int nx = src + 1 > PE - 1 ? PE - 1 : src + 1;
-                const K v = sk[nx];
+                const int src = ta ? ia : bi;
+                if constexpr (HAS_V) vout[e] = sv[src];
+                const K v = sk[src + 1];
                 ia += ta ? 1 : 0;
-                ib += ta ? 0 : 1;
+                bi += ta ? 0 : 1;
                 a = ta ? v : a;
                 b = ta ? b : v;
             }
@@ -432,6 +444,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_merge_oop(const K *__restrict__ 
     g.whi = 0;
     stage_tile_dma<K, THREADS, IPT>(in, g, sk);
     wait_dma();
+    if (threadIdx.x == 0) sk[g.n] = key_max<K>();   // B sentinel
     __syncthreads();
     K r[IPT];
     NoValL v[1];
@@ -461,7 +474,7 @@ static hipError_t merge_oop_t(const void *in, void *out, int64_t la, int64_t lb,
     const int64_t T = (int64_t)TH * IPT;
     const int64_t nt = (la + lb + T - 1) / T;
     if (nt <= 0) return hipSuccess;
-    const size_t lds = (size_t)(T + 2) * sizeof(K);
+    const size_t lds = (size_t)LdsPad<TH * IPT, IPT>::elems * sizeof(K);
     const void *fn = (const void *)&k_merge_oop<K, TH, IPT>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -638,7 +651,7 @@ void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, in
                    size_t *lds_bytes) {
     geom(esize_k, esize_v, cfg, threads, ipt, depth);
     int T = *threads * *ipt;
-    size_t pe = (size_t)(T + 2);
+    size_t pe = (size_t)(T + *ipt + 2);     // LdsPad
     *lds_bytes = pe * esize_k + pe * esize_v;
 }
 
