@@ -164,8 +164,10 @@ def bench_headline(torch, im, oracle, gen, dev, args):
     pristine = gen.torch_pair_uniform(la, lb, SEED + 20, dev)
     # leaf configuration chosen by the autotuner (outside the timed region)
     off1 = torch.tensor([0, la, n], dtype=torch.int64, device=dev)
-    chosen, tune_ms = im.autotune(pristine, off1, reps=3)
-    log("c2: autotune ms per config", ["%.3f" % m for m in tune_ms], "chosen", chosen)
+    tune_ms = []
+    if not args.no_tune:
+        chosen, tune_ms = im.autotune(pristine, off1, reps=3)
+        log("c2: autotune ms per config", ["%.3f" % m for m in tune_ms], "chosen", chosen)
     # the timed steps carry no stage events; a second pass with per-stage
     # events (which add small gaps between launches) feeds the roofline
     ms, _, bufs = timed_merges(torch, im, pristine, la, args.steps, args.warmup)
@@ -481,6 +483,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--forms", choices=["all", "none"], default="all")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (profiling runs: default leaf configuration)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device 3 times (the known-size "
+                         "reference that scales the HBM byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -498,6 +505,14 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     im.load()
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.ones(2 ** 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_copy": 2 ** 30}), flush=True)
+        return
 
     head = bench_headline(torch, im, oracle, gen, dev, args)
     n = head["n"]
