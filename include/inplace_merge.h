@@ -85,6 +85,8 @@ typedef struct {
     int32_t leaf_config;     /* leaf-merge configuration used (0..3)           */
     int32_t leaf_grid;       /* resident workgroups of the leaf merge          */
     int64_t split_fallbacks; /* FindMedian splits replaced by co-rank (device) */
+    int64_t fused_nodes;     /* nodes whose two division levels ran as one    */
+                             /* exchange (cycles of contiguous pieces) (dev.) */
 } im_stats;
 
 /* ---------------------------------------------------------------------- */

@@ -67,7 +67,7 @@ class _Stats(ctypes.Structure):
         ("reversed_elems", ctypes.c_int64), ("leaf_elems", ctypes.c_int64),
         ("search_probes", ctypes.c_int64), ("searches", ctypes.c_int64),
         ("leaf_config", ctypes.c_int32), ("leaf_grid", ctypes.c_int32),
-        ("split_fallbacks", ctypes.c_int64),
+        ("split_fallbacks", ctypes.c_int64), ("fused_nodes", ctypes.c_int64),
     ]
 
 

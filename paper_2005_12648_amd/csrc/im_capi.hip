@@ -194,10 +194,21 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->split_method = kSplitCorank;
     pl->rot_method = kRotLS;
     pl->cap_stash = 2 * (total / kCsSeg) + 16;
+    // Two division levels are fused into one exchange where the splits are
+    // symmetric (k_split); the rotation kernel cycles up to kMaxCyc pieces
+    // only for elements of at most 8 bytes.  IM_FUSE=0 turns it off.
+    const char *fz = std::getenv("IM_FUSE");
+    pl->fuse = (ek + ev <= 8 && !(fz && fz[0] == '0')) ? 1 : 0;
+    pl->pad2 = 0;
+    // A node is split only when it exceeds the leaf capacity, so a level has
+    // fewer than `per` split nodes; a level's node list takes children of
+    // the level before (2 per split) and grandchildren of fused nodes two
+    // levels before (4 per split); a fused node emits at most kMaxCuts/2
+    // cycles.
     int64_t per = total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
-    pl->cap_nodes = std::max<int64_t>(n_inst, 2 * per) + 16;
-    pl->cap_rot = pl->cap_nodes;
-    pl->cap_leaves = n_inst + 2 * (int64_t)lv * per + 16;
+    pl->cap_nodes = std::max<int64_t>(n_inst, 6 * per) + 16;
+    pl->cap_rot = pl->cap_nodes + 20 * per + 16;
+    pl->cap_leaves = n_inst + 6 * (int64_t)lv * per + 16;
     pl->cap_tiles = total / pl->tile + pl->cap_leaves + 16;
     return true;
 }
@@ -214,6 +225,7 @@ size_t carve(const Plan &pl, int64_t flag_slots, void *base, Work *w) {
     x.tile_flag = (unsigned *)take(sizeof(unsigned) * std::max<int64_t>(flag_slots, pl.cap_tiles));
     x.nodes[0] = (Node *)take(sizeof(Node) * pl.cap_nodes);
     x.nodes[1] = (Node *)take(sizeof(Node) * pl.cap_nodes);
+    x.nodes[2] = (Node *)take(sizeof(Node) * pl.cap_nodes);
     x.rot = (Rot *)take(sizeof(Rot) * pl.cap_rot);
     x.leaves = (Leaf *)take(sizeof(Leaf) * pl.cap_leaves);
     x.tile_start = (int64_t *)take(sizeof(int64_t) * pl.cap_leaves);
@@ -360,6 +372,7 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
     pl.split_method = split_method;
     pl.rot_method = rot_method;
+    if (split_method != kSplitCorank || rot_method != kRotLS) pl.fuse = 0;   // the paper's modes as such
     size_t need = carve(pl, ds->flag_cap, nullptr, nullptr);
     void *base = nullptr;
     int rc = acquire_ws(ds, need, &base);
@@ -595,6 +608,7 @@ int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream) {
     out->search_probes = (int64_t)c.probes;
     out->searches = (int64_t)c.searches;
     out->split_fallbacks = (int64_t)c.split_fallbacks;
+    out->fused_nodes = (int64_t)c.fused;
     if (c.error) return fail(IM_ERR_DEVICE, "device error bits " + std::to_string(c.error));
     return IM_OK;
 }

@@ -39,11 +39,21 @@ struct Node {
 
 // Partition exchange X|Y -> Y|X of [pos, pos+lx+ly).  lx == ly: one block
 // swap (a single linear-shifting step).  Otherwise three reversals.
+constexpr int kMaxCyc = 4;       // pieces of one cycle of a fused two-level exchange
+
+// An exchange of a level.  c == 0: the partition exchange X|Y -> Y|X of
+// [pos, pos+lx+ly).  c >= 2: a cycle of a fused two-level exchange: c
+// pieces of len elements at start[0..c), the piece at start[k] moves to
+// start[k+1 mod c].
 struct Rot {
     int64_t pos, lx, ly;
     int64_t w0;       // first work item of this exchange in its level
     int64_t nw;       // work items
     int64_t stash0;   // circular shifting: first stash slot (-1: none needed)
+    int64_t len;
+    int64_t start[kMaxCyc];
+    int32_t c;
+    int32_t pad;
 };
 
 // A pair that is merged without further division.  Its tiles are processed
@@ -71,6 +81,7 @@ struct Counters {
     unsigned long long searches;      // split searches
     unsigned long long levels_used;   // max level index that had nodes, +1
     unsigned long long split_fallbacks;  // FindMedian splits replaced by co-rank splits
+    unsigned long long fused;            // nodes whose two levels ran as one exchange
     unsigned int error;               // nonzero: a device-side check failed
     unsigned int pad;
 };
@@ -107,6 +118,8 @@ struct Plan {
     int32_t split_method;   // kSplitCorank or kSplitFindMedian
     int32_t rot_method;     // kRotLS or kRotCS
     int64_t cap_stash;      // circular shifting: stash slots per level
+    int32_t fuse;           // fuse two division levels into one exchange where possible
+    int32_t pad2;
 };
 
 // Split of a division node: the exact co-rank (symmetric or middle diagonal),
@@ -125,7 +138,7 @@ constexpr int kLeafCfgs = 4;   // leaf-merge tile configurations (im_leaf.hip)
 // Workspace carve-up (device pointers).
 struct Work {
     Counters *ctr;
-    Node *nodes[2];
+    Node *nodes[3];          // node lists of levels l, l+1, l+2 (ring)
     Rot *rot;
     Leaf *leaves;
     int64_t *tile_start;     // per leaf: first tile index (exclusive scan)

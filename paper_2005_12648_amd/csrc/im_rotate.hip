@@ -21,45 +21,68 @@
 
 namespace imerge {
 
-// Threads per workgroup by bytes moved per element (key + payload): each
-// thread holds kRotChunk / threads pairs, twice (software pipeline), so wider
-// elements take more threads to keep the registers per thread bounded.
-template <int BYTES>
-struct RotGeom {
-    static constexpr int threads = BYTES <= 4 ? 256 : (BYTES <= 8 ? 512 : 1024);
-    static constexpr int per = (int)(kRotChunk / threads);   // pairs per thread
-};
+template <typename EV> struct ValBytes { static constexpr int v = sizeof(EV); };
 
 struct NoVal {};
+template <> struct ValBytes<NoVal> { static constexpr int v = 0; };
 
-// One work item is a run of element pairs (X[t], Y[dir*t]) for t in
-// [0, lim): X starts at element xa and runs upwards; Y starts at yb and runs
-// upwards (dir = +1, a block swap) or downwards (dir = -1, the two ends of a
-// reversal).  Every item exchanges its pairs.  Both starts are the same for
-// every lane, so only a 32-bit offset varies per lane.
-struct PairItem {
-    int64_t xa, yb;
-    int32_t dir, lim;
+// Per element width (key + payload bytes): threads per workgroup, the most
+// pieces an item may cycle (fused two-level exchanges need up to kMaxCyc;
+// wider elements run only pairs, and their levels are not fused), and the
+// elements per thread and piece.  Every lane holds MAXC x PER elements per
+// item, twice (software pipeline).
+template <int BYTES>
+struct RotGeom {
+    static constexpr int threads = BYTES <= 4 ? 512 : 1024;
+    static constexpr int maxc = BYTES <= 8 ? kMaxCyc : 2;
+    static constexpr int per = (int)(kRotChunk / threads);
+};
+
+// One work item moves `lim` elements of each of c pieces: the element at
+// P_k[dir_k * t] goes to P_{k+1 mod c}[dir_{k+1} * t], t in [0, lim).  A
+// block swap is a cycle of two pieces running upwards; the two ends of a
+// reversal are two pieces, the second running downwards; a cycle of a fused
+// two-level exchange has up to kMaxCyc pieces running upwards.  The starts
+// are the same for every lane: only a 32-bit offset varies per lane.
+struct CycItem {
+    int64_t start[kMaxCyc];
+    int32_t dir[kMaxCyc];
+    int32_t c, lim;
 };
 
 // Item `local` of exchange R in this phase; lim = 0 if the phase has no such
 // item.
-//   |X| == |Y|: phase 0 swaps X with Y (one linear-shifting step).
+//   cycle (R.c >= 2): phase 0 moves chunk `local` of its pieces;
+//   |X| == |Y|: phase 0 swaps X with Y (one linear-shifting step);
 //   |X| != |Y|: phase 0 reverses X and Y (items of X first), phase 1
 //   reverses X|Y.
-__device__ __forceinline__ PairItem make_item(const Rot &R, int64_t local, int phase) {
-    PairItem it;
-    it.xa = 0;
-    it.yb = 0;
-    it.dir = 1;
+__device__ __forceinline__ CycItem make_item(const Rot &R, int64_t local, int phase) {
+    CycItem it;
+#pragma unroll
+    for (int k = 0; k < kMaxCyc; ++k) {
+        it.start[k] = 0;
+        it.dir[k] = 1;
+    }
+    it.c = 2;
     it.lim = 0;
+    if (R.c >= 2) {
+        if (phase != 0) return it;
+        const int64_t c0 = local * kRotChunk;
+        const int64_t n = R.len - c0;
+        if (n <= 0) return it;
+        it.c = R.c;
+#pragma unroll
+        for (int k = 0; k < kMaxCyc; ++k) it.start[k] = R.start[k] + c0;
+        it.lim = (int32_t)(n < kRotChunk ? n : kRotChunk);
+        return it;
+    }
     if (R.lx == R.ly) {
         if (phase != 0) return it;
         const int64_t c0 = local * kRotChunk;
         const int64_t n = R.lx - c0;
         if (n <= 0) return it;
-        it.xa = R.pos + c0;
-        it.yb = R.pos + R.lx + c0;
+        it.start[0] = R.pos + c0;
+        it.start[1] = R.pos + R.lx + c0;
         it.lim = (int32_t)(n < kRotChunk ? n : kRotChunk);
         return it;
     }
@@ -76,16 +99,16 @@ __device__ __forceinline__ PairItem make_item(const Rot &R, int64_t local, int p
     }
     const int64_t n = m / 2 - c0;          // pairs (t, m-1-t) for t < m/2
     if (n <= 0) return it;
-    it.xa = s + c0;
-    it.yb = s + m - 1 - c0;
-    it.dir = -1;
+    it.start[0] = s + c0;
+    it.start[1] = s + m - 1 - c0;
+    it.dir[1] = -1;
     it.lim = (int32_t)(n < kRotChunk ? n : kRotChunk);
     return it;
 }
 
-template <typename E, int PER>
-struct PairRegs {
-    E x[PER], y[PER];
+template <typename E, int MAXC, int PER>
+struct CycRegs {
+    E v[MAXC][PER];
 };
 
 __device__ __forceinline__ int64_t uni64(int64_t v) {
@@ -94,41 +117,49 @@ __device__ __forceinline__ int64_t uni64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <typename E, int TH, int PER>
-__device__ __forceinline__ void item_load(const E *__restrict__ p, const PairItem &it,
-                                          PairRegs<E, PER> &r) {
-    const E *X = p + uni64(it.xa);
-    const E *Y = p + uni64(it.yb);
-    const int dir = __builtin_amdgcn_readfirstlane(it.dir);
+template <typename E, int TH, int MAXC, int PER>
+__device__ __forceinline__ void item_load(const E *__restrict__ p, const CycItem &it,
+                                          CycRegs<E, MAXC, PER> &r) {
+    const int c = __builtin_amdgcn_readfirstlane(it.c);
     const int lim = __builtin_amdgcn_readfirstlane(it.lim);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int t = (int)threadIdx.x + u * TH;
-        if (t < lim) { r.x[u] = X[t]; r.y[u] = Y[dir * t]; }
+    for (int k = 0; k < MAXC; ++k) {
+        if (k < c) {
+            const E *P = p + uni64(it.start[k]);
+            const int dir = __builtin_amdgcn_readfirstlane(it.dir[k]);
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int t = (int)threadIdx.x + u * TH;
+                if (t < lim) r.v[k][u] = P[dir * t];
+            }
+        }
     }
 }
 
-template <typename E, int TH, int PER>
-__device__ __forceinline__ void item_store(E *__restrict__ p, const PairItem &it,
-                                           const PairRegs<E, PER> &r) {
-    E *X = p + uni64(it.xa);
-    E *Y = p + uni64(it.yb);
-    const int dir = __builtin_amdgcn_readfirstlane(it.dir);
+template <typename E, int TH, int MAXC, int PER>
+__device__ __forceinline__ void item_store(E *__restrict__ p, const CycItem &it,
+                                           const CycRegs<E, MAXC, PER> &r) {
+    const int c = __builtin_amdgcn_readfirstlane(it.c);
     const int lim = __builtin_amdgcn_readfirstlane(it.lim);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int t = (int)threadIdx.x + u * TH;
-        if (t < lim) { X[t] = r.y[u]; Y[dir * t] = r.x[u]; }
+    for (int k = 0; k < MAXC; ++k) {
+        if (k < c) {
+            const int d = k + 1 == c ? 0 : k + 1;      // piece k moves to piece d
+            E *P = p + uni64(it.start[d]);
+            const int dir = __builtin_amdgcn_readfirstlane(it.dir[d]);
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int t = (int)threadIdx.x + u * TH;
+                if (t < lim) P[dir * t] = r.v[k][u];
+            }
+        }
     }
 }
 
-template <typename EV, int PER>
-struct ValRegs { PairRegs<EV, PER> r; };
-template <int PER>
-struct ValRegs<NoVal, PER> {};
-
-template <typename EV> struct ValBytes { static constexpr int v = sizeof(EV); };
-template <> struct ValBytes<NoVal> { static constexpr int v = 0; };
+template <typename EV, int MAXC, int PER>
+struct ValRegs { CycRegs<EV, MAXC, PER> r; };
+template <int MAXC, int PER>
+struct ValRegs<NoVal, MAXC, PER> {};
 
 // A persistent grid walks the level's items, software pipelined: the loads
 // of the workgroup's next item are issued before the stores of the current
@@ -137,14 +168,15 @@ template <> struct ValBytes<NoVal> { static constexpr int v = 0; };
 // pipelined 5.1-5.3 TB/s; one workgroup per item reaches 5.2 TB/s, but an
 // empty launch of such a grid costs about 18 us against 6 us, and the
 // phase-1 launch is empty whenever a level has only block swaps.)
-template <typename EK, typename EV, int TH = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>::threads>
-__global__ __launch_bounds__(TH) void k_rotate(EK *__restrict__ keys, EV *__restrict__ vals,
-                                                        const Rot *__restrict__ rot,
-                                                        const Counters *__restrict__ ctr,
-                                                        int64_t cap_rot, int level, int phase) {
+template <typename EK, typename EV,
+          typename G = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>>
+__global__ __launch_bounds__(G::threads) void k_rotate(EK *__restrict__ keys, EV *__restrict__ vals,
+                                                       const Rot *__restrict__ rot,
+                                                       const Counters *__restrict__ ctr,
+                                                       int64_t cap_rot, int level, int phase) {
     constexpr bool HAS_V = !std::is_same<EV, NoVal>::value;
-    constexpr int PER = (int)(kRotChunk / TH);
-    if (phase == 1 && ctr->level_rev[level] == 0) return;   // only block swaps
+    constexpr int TH = G::threads, MAXC = G::maxc, PER = G::per;
+    if (phase == 1 && ctr->level_rev[level] == 0) return;   // only swaps and cycles
     const unsigned long long packed = ctr->level_rot[level];
     int64_t nrot = (int64_t)(packed >> kRotCountShift);
     if (nrot > cap_rot) nrot = cap_rot;
@@ -155,11 +187,11 @@ __global__ __launch_bounds__(TH) void k_rotate(EK *__restrict__ keys, EV *__rest
     R.w0 = 1;
     R.nw = 0;              // empty: forces a search for the first item
     bool have = false;     // an item is loaded and waits for its stores
-    PairItem cur;
-    PairRegs<EK, PER> kr;
-    ValRegs<EV, PER> vr;
+    CycItem cur;
+    CycRegs<EK, MAXC, PER> kr;
+    ValRegs<EV, MAXC, PER> vr;
     for (int64_t wi = blockIdx.x;; wi += gridDim.x) {
-        PairItem nx;
+        CycItem nx;
         nx.lim = 0;
         if (wi < nitems) {
             if (wi < R.w0 || wi >= R.w0 + R.nw) {
@@ -171,17 +203,17 @@ __global__ __launch_bounds__(TH) void k_rotate(EK *__restrict__ keys, EV *__rest
                 }
                 R = rot[lo];
             }
-            if (wi >= R.w0 && wi < R.w0 + R.nw)         // else a dropped exchange
+            if (wi >= R.w0 && wi < R.w0 + R.nw && R.c <= MAXC)   // else dropped / unsupported
                 nx = make_item(R, wi - R.w0, phase);
         }
         if (nx.lim > 0) {
-            PairRegs<EK, PER> kn;
-            ValRegs<EV, PER> vn;
-            item_load<EK, TH, PER>(keys, nx, kn);
-            if constexpr (HAS_V) item_load<EV, TH, PER>(vals, nx, vn.r);
+            CycRegs<EK, MAXC, PER> kn;
+            ValRegs<EV, MAXC, PER> vn;
+            item_load<EK, TH, MAXC, PER>(keys, nx, kn);
+            if constexpr (HAS_V) item_load<EV, TH, MAXC, PER>(vals, nx, vn.r);
             if (have) {
-                item_store<EK, TH, PER>(keys, cur, kr);
-                if constexpr (HAS_V) item_store<EV, TH, PER>(vals, cur, vr.r);
+                item_store<EK, TH, MAXC, PER>(keys, cur, kr);
+                if constexpr (HAS_V) item_store<EV, TH, MAXC, PER>(vals, cur, vr.r);
             }
             kr = kn;
             vr = vn;
@@ -191,24 +223,23 @@ __global__ __launch_bounds__(TH) void k_rotate(EK *__restrict__ keys, EV *__rest
         if (wi >= nitems) break;
     }
     if (have) {
-        item_store<EK, TH, PER>(keys, cur, kr);
-        if constexpr (HAS_V) item_store<EV, TH, PER>(vals, cur, vr.r);
+        item_store<EK, TH, MAXC, PER>(keys, cur, kr);
+        if constexpr (HAS_V) item_store<EV, TH, MAXC, PER>(vals, cur, vr.r);
     }
 }
 
 // Single exchange (stand-alone entry point): one descriptor built on the host.
-template <typename E, int TH = RotGeom<(int)sizeof(E)>::threads>
-__global__ __launch_bounds__(TH) void k_rotate_one(E *__restrict__ p, int64_t lx, int64_t ly,
-                                                   int phase, int64_t nitems) {
-    constexpr int PER = (int)(kRotChunk / TH);
+template <typename E, typename G = RotGeom<(int)sizeof(E)>>
+__global__ __launch_bounds__(G::threads) void k_rotate_one(E *__restrict__ p, int64_t lx, int64_t ly,
+                                                          int phase, int64_t nitems) {
     Rot R;
-    R.pos = 0; R.lx = lx; R.ly = ly; R.w0 = 0; R.nw = nitems;
+    R.pos = 0; R.lx = lx; R.ly = ly; R.w0 = 0; R.nw = nitems; R.c = 0; R.len = 0;
     for (int64_t wi = blockIdx.x; wi < nitems; wi += gridDim.x) {
-        const PairItem it = make_item(R, wi, phase);
+        const CycItem it = make_item(R, wi, phase);
         if (it.lim <= 0) continue;
-        PairRegs<E, PER> r;
-        item_load<E, TH, PER>(p, it, r);
-        item_store<E, TH, PER>(p, it, r);
+        CycRegs<E, 2, G::per> r;
+        item_load<E, G::threads, 2, G::per>(p, it, r);
+        item_store<E, G::threads, 2, G::per>(p, it, r);
     }
 }
 

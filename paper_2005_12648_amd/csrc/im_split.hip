@@ -116,6 +116,10 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
     r.w0 = (int64_t)(packed & kRotWorkMask);
     r.nw = nw;
     r.stash0 = stash0;
+    r.len = 0;
+    for (int q = 0; q < kMaxCyc; ++q) r.start[q] = 0;
+    r.c = 0;
+    r.pad = 0;
     w.rot[slot] = r;
     atomicAdd(&w.ctr->rotated, (unsigned long long)(lx + ly));
     if (lx != ly && pl.rot_method != kRotCS) {
@@ -161,6 +165,210 @@ __device__ __forceinline__ void emit_split(const Plan &pl, const Work &w, int le
     out[slot + 1] = r;
 }
 
+// ---------------------------------------------------------------------------
+// Fused two-level exchange.  With symmetric splits at a node and at both of
+// its children, the two levels of exchanges (Alg. 3's shift at the node,
+// then at each child) compose into one permutation of the node that takes
+//   A_LL A_LR A_RL A_RR B_LL B_LR B_RL B_RR  to  A_LL B_LL A_LR B_LR A_RL B_RL A_RR B_RR.
+// Cut into pieces that move as wholes (the block boundaries closed under the
+// permutation and its inverse), it is a handful of cycles of equal-length
+// contiguous pieces; moving each cycle once reads and writes every element
+// that changes place once, instead of twice for the elements that both
+// levels move (about 3/4 of the node moves instead of 2 x 1/2).
+// ---------------------------------------------------------------------------
+// The decomposition runs on the whole wave: lane q holds cut q (sorted, no
+// duplicates; kCutNone above the last), so a membership test is a six-step
+// lane binary search and an insert is one lane shift.  Every value below is
+// the same on all lanes of the wave except the per-lane cut and candidates.
+constexpr int kMaxCuts = 63;            // lane 63 always holds kCutNone
+constexpr int64_t kCutNone = INT64_MAX;
+
+// Blocks are given in source order (src[b] + len[b] == src[b + 1]); a block
+// of length 0 matches nothing.
+struct FusedPerm {
+    int64_t src[8], dst[8], len[8];
+};
+
+__device__ __forceinline__ int64_t fz_fwd(const FusedPerm &f, int64_t x) {
+    int64_t y = x;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        y = (x >= f.src[b] && x < f.src[b] + f.len[b]) ? f.dst[b] + (x - f.src[b]) : y;
+    return y;
+}
+__device__ __forceinline__ int64_t fz_inv(const FusedPerm &f, int64_t y) {
+    int64_t x = y;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        x = (y >= f.dst[b] && y < f.dst[b] + f.len[b]) ? f.src[b] + (y - f.dst[b]) : x;
+    return x;
+}
+
+// Number of cuts below v (the lanes hold a sorted list padded with kCutNone).
+__device__ __forceinline__ int wave_lower_bound(int64_t c, int64_t v) {
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(c, pos + step - 1, 64) < v) pos += step;
+    return pos;
+}
+
+// Adds the valid candidates of all lanes to the cut list.  False if it would
+// exceed kMaxCuts.
+__device__ __forceinline__ bool fz_add(int64_t &c, int &nc, int64_t cand, bool valid,
+                                       bool &changed) {
+    const int lane = threadIdx.x & 63;
+    // the search runs on every lane: a shuffle only reads lanes that execute it
+    const int64_t at = __shfl(c, wave_lower_bound(c, cand), 64);
+    bool fresh = valid && at != cand;
+    for (unsigned long long m = __ballot(fresh); m != 0; m = __ballot(fresh)) {
+        const int64_t v = __shfl(cand, __ffsll((long long)m) - 1, 64);
+        fresh = fresh && cand != v;
+        if (nc >= kMaxCuts) return false;
+        const int pos = __popcll(__ballot(c < v));
+        const int64_t below = __shfl(c, lane > 0 ? lane - 1 : 0, 64);
+        c = lane < pos ? c : (lane == pos ? v : below);
+        ++nc;
+        changed = true;
+    }
+    return true;
+}
+
+// Piece boundaries of the fused permutation of a node of S elements: the
+// block boundaries closed under the permutation (starts and ends of images)
+// and its inverse.  False if more than kMaxCuts are needed.
+__device__ __forceinline__ bool fz_closure(const FusedPerm &f, int64_t S, int64_t &c, int &nc) {
+    const int lane = threadIdx.x & 63;
+    c = kCutNone;
+    nc = 0;
+    bool changed = false;
+    int64_t b0 = lane == 8 ? S : 0;
+#pragma unroll
+    for (int b = 1; b < 8; ++b) b0 = lane == b ? f.src[b] : b0;
+    if (!fz_add(c, nc, b0, lane <= 8, changed)) return false;
+    for (int pass = 0; pass < 8; ++pass) {
+        changed = false;
+#pragma unroll
+        for (int col = 0; col < 4; ++col) {
+            const int64_t x = c;
+            const bool has = lane < nc;
+            int64_t cand;
+            bool valid;
+            if (col == 0) { cand = fz_fwd(f, x); valid = has && x < S; }
+            else if (col == 1) { cand = fz_inv(f, x); valid = has && x < S; }
+            else if (col == 2) { cand = fz_fwd(f, x - 1) + 1; valid = has && x > 0; }
+            else { cand = fz_inv(f, x - 1) + 1; valid = has && x > 0; }
+            if (!fz_add(c, nc, cand, valid, changed)) return false;
+        }
+        if (!changed) return true;
+    }
+    return false;
+}
+
+// Cycles of equal-length pieces between the cuts, one lane per piece;
+// written as exchange descriptors (slots and work items reserved at once, in
+// lane order).  False (nothing emitted) if an image is not a piece of the
+// same length or a cycle is longer than kMaxCyc.
+__device__ __forceinline__ bool fz_emit_cycles(const Plan &pl, const Work &w, int level,
+                                               int64_t base, const FusedPerm &f, int64_t c,
+                                               int nc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t hi = __shfl(c, lane < 63 ? lane + 1 : 63, 64);
+    const bool piece = lane + 1 < nc;
+    const int64_t L = piece ? hi - c : 0;
+    const int64_t img = piece ? fz_fwd(f, c) : c;
+    const bool moving = piece && img != c;
+    const int t = wave_lower_bound(c, img);
+    const int64_t ct = __shfl(c, t, 64);
+    const int64_t Lt = __shfl(L, t, 64);
+    if (__ballot(moving && (ct != img || t + 1 >= nc || Lt != L))) return false;
+    const int n1 = moving ? t : lane;
+    const int n2 = __shfl(n1, n1, 64);
+    const int n3 = __shfl(n1, n2, 64);
+    const int n4 = __shfl(n1, n3, 64);
+    const int clen = n2 == lane ? 2 : n3 == lane ? 3 : n4 == lane ? 4 : 0;
+    if (__ballot(moving && clen == 0)) return false;
+    const bool leader = moving && lane < n1 && (clen < 3 || lane < n2) && (clen < 4 || lane < n3);
+    const int64_t s1 = __shfl(c, n1, 64), s2 = __shfl(c, n2, 64), s3 = __shfl(c, n3, 64);
+    // inclusive scans of work items and cycles over the leader lanes
+    const int64_t nw = leader ? (L + kRotChunk - 1) / kRotChunk : 0;
+    int64_t sw = nw, mv = leader ? (int64_t)clen * L : 0;
+    int sc = leader ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t tw = __shfl(sw, lane >= d ? lane - d : 0, 64);
+        const int64_t tm = __shfl(mv, lane >= d ? lane - d : 0, 64);
+        const int tc = __shfl(sc, lane >= d ? lane - d : 0, 64);
+        if (lane >= d) { sw += tw; mv += tm; sc += tc; }
+    }
+    const int64_t total_w = __shfl(sw, 63, 64), moved = __shfl(mv, 63, 64);
+    const int ncyc = __shfl(sc, 63, 64);
+    if (ncyc == 0) return true;
+    unsigned long long packed = 0;
+    if (lane == 0) {
+        packed = atomicAdd(&w.ctr->level_rot[level],
+                           ((unsigned long long)ncyc << kRotCountShift) |
+                               (unsigned long long)total_w);
+        atomicAdd(&w.ctr->rotated, (unsigned long long)moved);
+    }
+    packed = __shfl(packed, 0, 64);
+    const int64_t slot0 = (int64_t)(packed >> kRotCountShift);
+    if (slot0 + ncyc > pl.cap_rot) {
+        if (lane == 0) atomicOr(&w.ctr->error, kErrCapacity);
+        return true;
+    }
+    if (leader) {
+        Rot r;
+        r.pos = base; r.lx = 0; r.ly = 0;
+        r.w0 = (int64_t)(packed & kRotWorkMask) + sw - nw;
+        r.nw = nw;
+        r.stash0 = -1;
+        r.len = L;
+        r.start[0] = base + c;
+        r.start[1] = base + s1;
+        r.start[2] = clen > 2 ? base + s2 : 0;
+        r.start[3] = clen > 3 ? base + s3 : 0;
+        r.c = clen;
+        r.pad = 0;
+        w.rot[slot0 + sc - 1] = r;
+    }
+    return true;
+}
+
+// The fused exchange of a node (all lanes of the wave).  False (nothing
+// emitted) if the permutation does not fit.
+__device__ __forceinline__ bool emit_fused(const Plan &pl, const Work &w, int level, int64_t base,
+                                           const FusedPerm &f, int64_t S) {
+    int64_t c;
+    int nc;
+    if (!fz_closure(f, S, c, nc)) return false;
+    return fz_emit_cycles(pl, w, level, base, f, c, nc);
+}
+
+__device__ __forceinline__ void emit_node(const Plan &pl, const Work &w, int level, Node *out,
+                                          const Node &nd) {
+    unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level], 1ull);
+    if ((int64_t)slot >= pl.cap_nodes) {
+        atomicOr(&w.ctr->error, kErrCapacity);
+        return;
+    }
+    out[slot] = nd;
+}
+
+// What a child of a fused node does at the next level, read on the original
+// layout: 0 = nothing to split (empty part, in order, or a leaf), 1 = a
+// symmetric split (block swap), 2 = anything else (not fusable).
+template <typename K>
+__device__ __forceinline__ int child_kind(const Plan &pl, const K *A, int64_t la, const K *B,
+                                          int64_t lb) {
+    if (la == 0 || lb == 0) return 0;
+    if (A[la - 1] <= B[0]) return 0;
+    if (A[0] > B[lb - 1]) return 2;                    // a whole-child exchange
+    if (la + lb <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) return 0;
+    const int64_t S = la + lb, mx = la > lb ? la : lb;
+    return (mx * 16 <= S * 9) ? 1 : 2;
+}
+
 // One lane per node classifies it (early exits, leaf); the nodes of a wave
 // that must be split are then searched one after another by the whole wave
 // with the cooperative 64-ary co-rank (a handful of dependent rounds).
@@ -171,8 +379,12 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
                                                          const MlpDev *__restrict__ mlp) {
     const unsigned long long cnt_raw = w.ctr->level_nodes[level];
     const int64_t cnt = (int64_t)cnt_raw < pl.cap_nodes ? (int64_t)cnt_raw : pl.cap_nodes;
-    const Node *in = w.nodes[level & 1];
-    Node *out = w.nodes[(level + 1) & 1];
+    const Node *in = w.nodes[level % 3];
+    Node *out = w.nodes[(level + 1) % 3];
+    Node *out2 = w.nodes[(level + 2) % 3];
+    // two levels fused only when the grandchildren still get a level of
+    // their own (the last level only classifies)
+    const bool may_fuse = pl.fuse && level + 2 <= pl.max_levels - 1;
     const int lane = threadIdx.x & 63;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -248,8 +460,91 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
             } else {
                 i = corank_group<64>(A, la, B, lb, kk, rounds);
             }
+            const int64_t j = kk - i;
+            bool fused = false;
+            if (may_fuse && kk == la && la - i > 0 && j > 0) {
+                // children on the original layout: L = A[0,i) | B[0,j),
+                // R = A[i,la) | B[j,lb)
+                const int kl = child_kind(pl, A, i, B, j);
+                const int kr = child_kind(pl, A + i, la - i, B + j, lb - j);
+                if (kl != 2 && kr != 2) {
+                    int64_t il = i, ir = la - i;          // kept whole: (|A_X|, |B_X|)
+                    ++searches;
+                    if (kl == 1) {
+                        if (LEARNED) {
+                            const int64_t k0 = __shfl(nd.k0, src, 64);
+                            const int64_t i0 = __shfl(nd.i0, src, 64);
+                            const int inst = __shfl(nd.inst, src, 64);
+                            int64_t o0 = offsets[2 * inst], o1 = offsets[2 * inst + 1],
+                                    o2 = offsets[2 * inst + 2];
+                            il = corank_group_learned<64>(A, i, B, j, i, mlp, k0 + i, o2 - o0,
+                                                          o1 - o0, i0, rounds);
+                        } else {
+                            il = corank_group<64>(A, i, B, j, i, rounds);
+                        }
+                    }
+                    if (kr == 1) {
+                        if (LEARNED) {
+                            const int64_t k0 = __shfl(nd.k0, src, 64);
+                            const int64_t i0 = __shfl(nd.i0, src, 64);
+                            const int inst = __shfl(nd.inst, src, 64);
+                            int64_t o0 = offsets[2 * inst], o1 = offsets[2 * inst + 1],
+                                    o2 = offsets[2 * inst + 2];
+                            ir = corank_group_learned<64>(A + i, la - i, B + j, lb - j, la - i, mlp,
+                                                          k0 + kk + (la - i), o2 - o0, o1 - o0,
+                                                          i0 + i, rounds);
+                        } else {
+                            ir = corank_group<64>(A + i, la - i, B + j, lb - j, la - i, rounds);
+                        }
+                    }
+                    // child splits (il, jl) of L and (ir, jr) of R; the
+                    // whole wave decomposes the permutation
+                    const int64_t jl = kl == 1 ? i - il : j;
+                    const int64_t jr = kr == 1 ? (la - i) - ir : lb - j;
+                    FusedPerm f;
+                    f.src[0] = 0;            f.len[0] = il;               f.dst[0] = 0;
+                    f.src[1] = il;           f.len[1] = i - il;           f.dst[1] = il + jl;
+                    f.src[2] = i;            f.len[2] = ir;               f.dst[2] = i + j;
+                    f.src[3] = i + ir;       f.len[3] = la - i - ir;      f.dst[3] = i + j + ir + jr;
+                    f.src[4] = la;           f.len[4] = jl;               f.dst[4] = il;
+                    f.src[5] = la + jl;      f.len[5] = j - jl;           f.dst[5] = i + jl;
+                    f.src[6] = la + j;       f.len[6] = jr;               f.dst[6] = i + j + ir;
+                    f.src[7] = la + j + jr;  f.len[7] = lb - j - jr;      f.dst[7] = la + j + jr;
+                    fused = emit_fused(pl, w, level, base, f, la + lb);
+                    if (fused && lane == src) {
+                        atomicAdd(&w.ctr->fused, 1ull);
+                        // grandchildren (or whole children) go to level + 2
+                        Node g;
+                        g.inst = nd.inst;
+                        g.pad = 0;
+                        if (kl == 1) {
+                            g.base = nd.base; g.la = il; g.lb = jl; g.k0 = nd.k0; g.i0 = nd.i0;
+                            emit_node(pl, w, level + 2, out2, g);
+                            g.base = nd.base + il + jl; g.la = i - il; g.lb = j - jl;
+                            g.k0 = nd.k0 + il + jl; g.i0 = nd.i0 + il;
+                            emit_node(pl, w, level + 2, out2, g);
+                        } else {
+                            g.base = nd.base; g.la = i; g.lb = j; g.k0 = nd.k0; g.i0 = nd.i0;
+                            emit_node(pl, w, level + 2, out2, g);
+                        }
+                        const int64_t rb = nd.base + kk;
+                        if (kr == 1) {
+                            g.base = rb; g.la = ir; g.lb = jr; g.k0 = nd.k0 + kk;
+                            g.i0 = nd.i0 + i;
+                            emit_node(pl, w, level + 2, out2, g);
+                            g.base = rb + ir + jr; g.la = la - i - ir; g.lb = lb - j - jr;
+                            g.k0 = nd.k0 + kk + ir + jr; g.i0 = nd.i0 + i + ir;
+                            emit_node(pl, w, level + 2, out2, g);
+                        } else {
+                            g.base = rb; g.la = la - i; g.lb = lb - j; g.k0 = nd.k0 + kk;
+                            g.i0 = nd.i0 + i;
+                            emit_node(pl, w, level + 2, out2, g);
+                        }
+                    }
+                }
+            }
             if (lane != src) continue;
-            emit_split(pl, w, level, out, nd, i, kk - i);
+            if (!fused) emit_split(pl, w, level, out, nd, i, j);
         }
     }
     if (pl.split_method == kSplitFindMedian) {
