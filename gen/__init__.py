@@ -19,6 +19,10 @@ Workloads (sizes and distributions of the target configurations):
                      sorted.
   * ``paper_w1``  -- the paper's own generator (Sec. 4, test cases):
                      a[0] = 0, a[i] = a[i-1] + 5 * rand01(); int32 by floor.
+  * ``rows``      -- wide elements (Sec. 4 test cases: elements of several
+                     bytes compared on their first word): an (n, w) array whose
+                     column 0 holds each run's sorted keys (uniform in [0, hi),
+                     or the W1 walk) and whose other words are uniform payload.
 """
 from __future__ import annotations
 
@@ -147,6 +151,29 @@ def make(name: str, scale: int = 0):
 # generator on the GPU so full-size benchmark inputs take milliseconds).
 # Values differ from the numpy draws above; both are seeded and synthetic.
 # --------------------------------------------------------------------------
+def rows_pair(la: int, lb: int, words: int, seed: int, hi: int = 2 ** 31, dtype=np.int32,
+              keys: np.ndarray | None = None) -> np.ndarray:
+    """(la+lb, words) rows: column 0 = sorted keys of A then of B (uniform in
+    [0, hi), or the given A|B keys), other columns uniform payload."""
+    if keys is None:
+        keys = pair_uniform(la, lb, seed, hi=hi, dtype=dtype)
+    r = _rng(seed + 7)
+    rows = r.integers(0, 2 ** 31, size=(la + lb, words), dtype=np.int64).astype(dtype)
+    rows[:, 0] = keys.astype(dtype)
+    return rows
+
+
+def torch_rows_pair(la: int, lb: int, words: int, seed: int, device, dtype=None):
+    """Device form of rows_pair (keys uniform in [0, 2^31))."""
+    import torch
+    dtype = dtype or torch.int32
+    g = _tgen(seed + 7, device)
+    rows = torch.randint(0, 2 ** 31, (la + lb, words), generator=g, device=device,
+                         dtype=torch.int64).to(dtype)
+    rows[:, 0] = torch_pair_uniform(la, lb, seed, device, dtype=dtype)
+    return rows
+
+
 def _tgen(seed: int, device):
     import torch
     g = torch.Generator(device=device)

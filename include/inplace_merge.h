@@ -107,6 +107,30 @@ int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B,
                      int key_dtype, int val_dtype, hipStream_t stream);
 
 /* ---------------------------------------------------------------------- */
+/* Wide elements (Sec. 4 test cases: elements of 4 to 65540 bytes whose    */
+/* first 4 bytes are the compared key; Sec. 5 on minimum data movement     */
+/* for large elements).                                                    */
+/* ---------------------------------------------------------------------- */
+
+/* Merge rows in place: data holds L_A+L_B rows of row_bytes bytes each
+ * (array of structures); rows [0, L_A) and [L_A, L_A+L_B) are each ascending
+ * by the key stored in the first bytes of a row, of type key_dtype (4 or 8
+ * bytes).  Stable: equal keys keep A's rows first, and every row moves as a
+ * whole.  The division and the exchanges are those of inplace_merge (the
+ * exchanges move 4-byte words); the leaves gather rows into registers in
+ * merged order.  Requirements (else IM_ERR_INVALID_ARG): row_bytes a
+ * multiple of 4 and of the key size; data aligned to the key size; at most
+ * 65536 bytes per row when row_bytes is a multiple of 16 and data is
+ * 16-byte aligned, 32768 when a multiple of 8, 16384 otherwise.  IM_CHECK=1
+ * checks the runs' keys.  The element counts of im_stats count rows. */
+int inplace_merge_rows(void *data, int64_t L_A, int64_t L_B, int64_t row_bytes,
+                       int key_dtype, hipStream_t stream);
+
+/* Workspace bytes a rows merge of `rows` rows needs (see
+ * inplace_merge_workspace_bytes). */
+size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int key_dtype);
+
+/* ---------------------------------------------------------------------- */
 /* Batched segmented merge: n independent instances in one buffer.         */
 /* ---------------------------------------------------------------------- */
 

@@ -10,6 +10,10 @@ Contents and the passage each one follows:
   runs A|B become one sorted run.  Stable reading: ties take A first (the
   per-pair ``std::inplace_merge`` of Alg. 2/3 is stable).  Plain two-finger
   merge in C (``oracle.c``), out of place, copied back.
+* :func:`merge_rows` -- the same stable merge for wide elements (Sec. 4 test
+  cases: elements of several bytes compared on their first bytes): the rows
+  are ordered by the key in their first column, ties take A, and each row
+  moves whole.  The order comes from :func:`merge_kv` on (key, row index).
 * :func:`corank` -- number of A elements among the first k merged outputs: the
   "optimal" split of Sec. 3.1 for an arbitrary output rank, by walking the merge.
 * :func:`rotate`, :func:`rotate_ls`, :func:`rotate_cs` -- the partition exchange
@@ -127,6 +131,17 @@ def merge_kv(keys: np.ndarray, vals: np.ndarray, la: int):
     if rc != 0:
         raise MemoryError("oracle merge_kv: allocation failed")
     return k, v
+
+
+def merge_rows(rows: np.ndarray, la: int) -> np.ndarray:
+    """Stable merge of the rows of a 2-D array: rows[:la] and rows[la:] are
+    ascending by column 0; ties take A; rows move whole (Sec. 4 elements)."""
+    r = np.ascontiguousarray(rows)
+    if r.ndim != 2 or not 0 <= la <= r.shape[0]:
+        raise ValueError("shape mismatch")
+    idx = np.arange(r.shape[0], dtype=np.uint64)
+    _, order = merge_kv(r[:, 0].copy(), idx, la)
+    return r[order.astype(np.int64)]
 
 
 def corank(a: np.ndarray, b: np.ndarray, ks) -> np.ndarray:

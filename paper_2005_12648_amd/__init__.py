@@ -28,6 +28,7 @@ __all__ = [
     "MergeGraph", "set_config", "autotune", "LEAF_CONFIGS",
     "inplace_merge_variant", "divide", "rotate_cs", "merge_out_of_place",
     "inplace_merge_buffered", "SPLIT_CORANK", "SPLIT_FINDMEDIAN", "ROTATE_LS", "ROTATE_CS",
+    "inplace_merge_rows", "rows_workspace_bytes",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -94,6 +95,7 @@ def load():
     sig = {
         "inplace_merge": [vp, i64, i64, c_int, vp],
         "inplace_merge_kv": [vp, vp, i64, i64, c_int, c_int, vp],
+        "inplace_merge_rows": [vp, i64, i64, i64, c_int, vp],
         "batched_inplace_merge": [vp, vp, i64, i64, i64, c_int, vp],
         "batched_inplace_merge_kv": [vp, vp, vp, i64, i64, i64, c_int, c_int, vp],
         "inplace_merge_sort": [vp, i64, c_int, vp],
@@ -133,6 +135,8 @@ def load():
         f.restype = c_int
     lib.inplace_merge_workspace_bytes.argtypes = [i64, i64, c_int]
     lib.inplace_merge_workspace_bytes.restype = ctypes.c_size_t
+    lib.inplace_merge_rows_workspace_bytes.argtypes = [i64, i64, c_int]
+    lib.inplace_merge_rows_workspace_bytes.restype = ctypes.c_size_t
     lib.inplace_merge_last_error.argtypes = []
     lib.inplace_merge_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -191,6 +195,31 @@ def inplace_merge_kv(keys: torch.Tensor, vals: torch.Tensor, la: int, stream=Non
                                        ctypes.c_void_p(vals.data_ptr()), la, n - la,
                                        _key_code(keys), _key_code(vals), _stream(stream)))
     return keys, vals
+
+
+def inplace_merge_rows(rows: torch.Tensor, la: int, stream=None) -> torch.Tensor:
+    """Stable in-place merge of the rows of a contiguous 2-D tensor (n, w):
+    rows[:la] and rows[la:] are ascending by column 0 (the key, of the
+    tensor's dtype); every row moves as a whole.  Returns rows."""
+    if not isinstance(rows, torch.Tensor):
+        raise TypeError("rows must be a torch.Tensor")
+    if not rows.is_cuda:
+        raise ValueError("rows must live on a HIP device (no CPU path exists)")
+    if rows.dim() != 2 or not rows.is_contiguous():
+        raise ValueError("rows must be a contiguous 2-D tensor")
+    n = rows.shape[0]
+    if not 0 <= la <= n:
+        raise ValueError("la out of range")
+    row_bytes = rows.shape[1] * rows.element_size()
+    with torch.cuda.device(rows.device):
+        _check(load().inplace_merge_rows(ctypes.c_void_p(rows.data_ptr()), la, n - la,
+                                         row_bytes, _key_code(rows), _stream(stream)))
+    return rows
+
+
+def rows_workspace_bytes(rows: int, row_bytes: int, key_dtype=torch.int32) -> int:
+    """Workspace bytes of a rows merge (0 if the arguments are invalid)."""
+    return int(load().inplace_merge_rows_workspace_bytes(rows, row_bytes, _DT[key_dtype]))
 
 
 def batched_inplace_merge(data: torch.Tensor, offsets: torch.Tensor, max_instance: int = 0,

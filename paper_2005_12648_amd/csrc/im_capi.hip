@@ -94,6 +94,7 @@ struct DevState {
     hipEvent_t done = nullptr;   // last enqueued use of the workspace
     bool done_valid = false;
     int grid[kLeafCfgs][2][3] = {};   // leaf grid by (config, key 4/8, payload 0/4/8)
+    int rows_grid[4][3] = {};         // rows leaf grid by (key code, chunk 4/8/16)
     // Autotuned leaf configuration by (key 4/8, payload 0/4/8, floor(log2 of
     // the mean instance size)); -1: not tuned.
     int tuned[2][3][64];
@@ -200,6 +201,8 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     const char *fz = std::getenv("IM_FUSE");
     pl->fuse = (ek + ev <= 8 && !(fz && fz[0] == '0')) ? 1 : 0;
     pl->pad2 = 0;
+    pl->row_stride = 0;
+    pl->rot_scale = 1;
     // A node is split only when it exceeds the leaf capacity, so a level has
     // fewer than `per` split nodes; a level's node list takes children of
     // the level before (2 per split) and grandchildren of fused nodes two
@@ -209,6 +212,59 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->cap_nodes = std::max<int64_t>(n_inst, 6 * per) + 16;
     pl->cap_rot = pl->cap_nodes + 20 * per + 16;
     pl->cap_leaves = n_inst + 6 * (int64_t)lv * per + 16;
+    pl->cap_tiles = total / pl->tile + pl->cap_leaves + 16;
+    return true;
+}
+
+// Rows of row_bytes bytes moved in chunks of ch bytes (row_bytes % ch == 0).
+int chunk_index(int ch) { return ch == 4 ? 0 : (ch == 8 ? 1 : 2); }
+
+// Plan of a rows merge: the same division (keys read row_bytes apart,
+// exchanges in 4-byte units), leaves merged by k_leafrows: tiles of R rows,
+// two tiles read ahead per workgroup, so a leaf may have 2G tiles.
+bool make_plan_rows(DevState *ds, int key_dt, int64_t row_bytes, int ch, int64_t total,
+                    Plan *pl) {
+    int &gc = ds->rows_grid[key_dt][chunk_index(ch)];
+    if (gc == 0) gc = rows_grid(key_dt, ch);
+    int G = gc;
+    const int R = rows_tile(row_bytes, ch);
+    if (G <= 0 || R < 1) return false;
+    if (const char *g_env = std::getenv("IM_LEAF_GRID")) {
+        long v = std::strtol(g_env, nullptr, 10);
+        if (v >= 1 && v < G) G = (int)v;
+    }
+    int64_t tiles_per_leaf = 2 * (int64_t)G;
+    if (const char *cap_env = std::getenv("IM_LEAF_TILES")) {
+        long v = std::strtol(cap_env, nullptr, 10);
+        if (v >= 1 && v <= 2 * (int64_t)G) tiles_per_leaf = v;
+    }
+    pl->cfg = 0;
+    pl->n_inst = 1;
+    pl->total = total;
+    pl->tile = R;
+    pl->leaf_cap = tiles_per_leaf * R;
+    pl->leaf_span = (tiles_per_leaf > 2 ? tiles_per_leaf - 2 : 0) * R;
+    pl->grid_leaf = G;
+    const double stop = (double)std::max<int64_t>(pl->leaf_cap, 2 * pl->leaf_span);
+    int lv = 1;
+    double sz = (double)total;
+    while (sz > stop && lv < kMaxLevels) {
+        sz = sz * 9.0 / 16.0 + 1.0;
+        ++lv;
+    }
+    pl->max_levels = lv;
+    pl->split_method = kSplitCorank;
+    pl->rot_method = kRotLS;
+    pl->cap_stash = 16;
+    const char *fz = std::getenv("IM_FUSE");
+    pl->fuse = (fz && fz[0] == '0') ? 0 : 1;   // exchanges move 4-byte units
+    pl->pad2 = 0;
+    pl->row_stride = row_bytes / key_size(key_dt);
+    pl->rot_scale = row_bytes / 4;
+    int64_t per = total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
+    pl->cap_nodes = std::max<int64_t>(1, 6 * per) + 16;
+    pl->cap_rot = pl->cap_nodes + 20 * per + 16;
+    pl->cap_leaves = 1 + 6 * (int64_t)lv * per + 16;
     pl->cap_tiles = total / pl->tile + pl->cap_leaves + 16;
     return true;
 }
@@ -315,11 +371,14 @@ int read_error_bits(Counters *ctr, hipStream_t s, unsigned *bits) {
 int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
                      int64_t n_inst, int64_t la, int64_t lb, const MlpDev *mlp, const Plan &pl,
                      const Work &w, bool check, bool prof, hipStream_t s) {
-    const int ek = key_size(key_dt);
+    // rows are exchanged as 4-byte units (the descriptors are scaled)
+    const int ek = pl.row_stride > 0 ? 4 : key_size(key_dt);
     IM_HIP(launch_init(pl, w, d_offsets, la, lb, s), "launch init");
     const int64_t *offs = d_offsets ? d_offsets : w.offsets1;
     if (check) {
-        IM_HIP(launch_check_sorted(key_dt, keys, offs, n_inst, w.ctr, s), "launch check");
+        IM_HIP(launch_check_sorted(key_dt, keys, offs, n_inst, w.ctr,
+                                   pl.row_stride > 0 ? pl.row_stride : 1, s),
+               "launch check");
         unsigned bits = 0;
         int rc = read_error_bits(w.ctr, s, &bits);
         if (rc) return rc;
@@ -357,19 +416,31 @@ void record_stats(const Plan &pl, const Work &w) {
 
 // The whole merge: division levels, leaf planning, tile co-ranks, leaf merge.
 // cfg_override >= 0 forces a leaf configuration (autotuner).
+// Rows mode of run_pipeline: row bytes (0: packed keys) and chunk bytes.
+struct RowsArg {
+    int64_t bytes;
+    int ch;
+};
+
 int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
                  int64_t n_inst, int64_t total, int64_t max_inst, int64_t la, int64_t lb,
                  const MlpDev *mlp, hipStream_t s, int cfg_override = -1,
-                 int split_method = kSplitCorank, int rot_method = kRotLS) {
+                 int split_method = kSplitCorank, int rot_method = kRotLS,
+                 RowsArg rows = RowsArg{0, 0}) {
     int dev = 0;
     DevState *ds = dev_state(&dev);
     if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
     std::lock_guard<std::mutex> lock(ds->mu);
     const int ek = key_size(key_dt);
-    const int cfg = choose_cfg(ds, ek, ev, n_inst, total, cfg_override);
     Plan pl;
-    if (!make_plan(ds, ek, ev, n_inst, total, max_inst, cfg, &pl))
-        return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
+    if (rows.bytes > 0) {
+        if (!make_plan_rows(ds, key_dt, rows.bytes, rows.ch, total, &pl))
+            return fail(IM_ERR_HIP, "could not size the rows leaf merge grid");
+    } else {
+        const int cfg = choose_cfg(ds, ek, ev, n_inst, total, cfg_override);
+        if (!make_plan(ds, ek, ev, n_inst, total, max_inst, cfg, &pl))
+            return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
+    }
     pl.split_method = split_method;
     pl.rot_method = rot_method;
     if (split_method != kSplitCorank || rot_method != kRotLS) pl.fuse = 0;   // the paper's modes as such
@@ -406,7 +477,10 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
                           prof, s);
     if (rc) return rc;
     hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
-    IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
+    if (rows.bytes > 0)
+        IM_HIP(launch_leafrows(key_dt, rows.ch, keys, rows.bytes, pl, w, s), "launch rows merge");
+    else
+        IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
     prof_end(e4, kStLeafMerge, 1, s);
     rc = ws_leave(ds, s);
     if (rc) return rc;
@@ -493,6 +567,61 @@ int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B, int key_d
     if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
     return run_pipeline(key_dtype, key_size(val_dtype), keys, vals, nullptr, 1, L_A + L_B,
                         L_A + L_B, L_A, L_B, nullptr, stream);
+}
+
+// Rows: the largest chunk (16, 8 or 4 bytes) that divides the row and the
+// data address; 0 if the row shape is not supported.
+static int rows_chunk(const void *data, int64_t row_bytes, int key_dtype, const char **why) {
+    const int kb = key_size(key_dtype);
+    if (row_bytes < kb || row_bytes % kb != 0 || row_bytes % 4 != 0) {
+        *why = "row bytes must be a positive multiple of the key size and of 4";
+        return 0;
+    }
+    const uintptr_t a = (uintptr_t)data;
+    if (a % (uintptr_t)kb != 0) {
+        *why = "data must be aligned to the key size";
+        return 0;
+    }
+    int ch = 4;
+    if (row_bytes % 16 == 0 && a % 16 == 0) ch = 16;
+    else if (row_bytes % 8 == 0 && a % 8 == 0) ch = 8;
+    if (rows_tile(row_bytes, ch) < 1) {
+        *why = "row too large: at most 65536 bytes for rows of 16-byte multiples "
+               "(32768 for 8-byte, 16384 for 4-byte multiples)";
+        return 0;
+    }
+    return ch;
+}
+
+int inplace_merge_rows(void *data, int64_t L_A, int64_t L_B, int64_t row_bytes, int key_dtype,
+                       hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, key_dtype);
+    if (rc) return rc;
+    if (row_bytes <= 0) return fail(IM_ERR_INVALID_ARG, "row bytes must be positive");
+    if (L_A + L_B > 0 && (L_A + L_B) > (int64_t(1) << 46) / row_bytes)
+        return fail(IM_ERR_INVALID_ARG, "array too large");
+    if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
+    const char *why = "";
+    const int ch = rows_chunk(data, row_bytes, key_dtype, &why);
+    if (ch == 0) return fail(IM_ERR_INVALID_ARG, why);
+    return run_pipeline(key_dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
+                        nullptr, stream, -1, kSplitCorank, kRotLS, RowsArg{row_bytes, ch});
+}
+
+size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int key_dtype) {
+    if (!valid_dtype(key_dtype) || rows < 0 || row_bytes <= 0) return 0;
+    DevState *ds = dev_state(nullptr);
+    if (!ds) return 0;
+    std::lock_guard<std::mutex> lock(ds->mu);
+    size_t need = 0;
+    for (int ch : {4, 8, 16}) {
+        if (row_bytes % ch != 0 || rows_tile(row_bytes, ch) < 1) continue;
+        Plan pl;
+        if (!make_plan_rows(ds, key_dtype, row_bytes, ch, std::max<int64_t>(rows, 1), &pl))
+            return 0;
+        need = std::max(need, carve(pl, 0, nullptr, nullptr));
+    }
+    return need;
 }
 
 int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n, int64_t total_elems,

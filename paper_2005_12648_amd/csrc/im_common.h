@@ -120,6 +120,11 @@ struct Plan {
     int64_t cap_stash;      // circular shifting: stash slots per level
     int32_t fuse;           // fuse two division levels into one exchange where possible
     int32_t pad2;
+    // Rows (elements of several words ordered by their leading key): the
+    // row length in key units (0: packed keys), and the number of 4-byte
+    // exchange units per element (1: exchanges move whole elements).
+    int64_t row_stride;
+    int64_t rot_scale;
 };
 
 // Split of a division node: the exact co-rank (symmetric or middle diagonal),
@@ -194,8 +199,16 @@ int merge_oop_tile(int esize);
 hipError_t launch_tile_diagonals(int64_t n, int64_t tile, int64_t *d_k, hipStream_t s);
 hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int64_t lb,
                             const int64_t *d_rank, hipStream_t s);
+// Checked mode: flags runs that are not ascending (keys `stride` key units
+// apart: 1 for packed keys, the row length for rows).
 hipError_t launch_check_sorted(int key, const void *data, const int64_t *d_offsets,
-                               int64_t n_inst, Counters *ctr, hipStream_t s);
+                               int64_t n_inst, Counters *ctr, int64_t stride, hipStream_t s);
+// Wide rows (im_leaf.hip): rows per tile for (row bytes, chunk bytes), the
+// resident grid of the rows leaf merge, and its cooperative launch.
+int rows_tile(int64_t row_bytes, int ch);
+int rows_grid(int key, int ch);
+hipError_t launch_leafrows(int key, int ch, void *data, int64_t row_bytes, const Plan &pl,
+                           const Work &w, hipStream_t s);
 
 // Merge sort helpers.
 int sort_tile_elems(int esize);

@@ -166,6 +166,36 @@ __device__ __forceinline__ void buf_store(E v, __amdgpu_buffer_rsrc_t r, int off
 
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Wait until every tile that reads this window has its inputs on chip.
+// Flags are touched only with relaxed device-scope atomics: the readers'
+// loads have returned before they publish, and an acquire/release fence at
+// device scope would write back or invalidate this XCD's whole L2 on every
+// poll.  Returns false if the bounded wait expired.
+template <int THREADS>
+__device__ __forceinline__ bool wait_window(const TileGeo &g, const Plan &pl, const Work &w) {
+    if (g.ntiles <= 1) return true;
+    int bad = 0;
+    for (int q = g.wlo + (int)threadIdx.x; q <= g.whi && !bad; q += THREADS) {
+        if (q == g.local) continue;
+        const unsigned *f = &w.tile_flag[g.tbase + q];
+        unsigned spins = 0;
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pl.epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) { bad = 1; break; }
+        }
+    }
+    bad = __syncthreads_or(bad);
+    if (bad && threadIdx.x == 0) atomicOr(&w.ctr->error, kErrBarrierSpin);
+    return !bad;
+}
+
+// "Inputs read": the tile's loads have returned in every thread.
+__device__ __forceinline__ void publish_read(const TileGeo &g, const Plan &pl, const Work &w) {
+    if (g.ntiles > 1 && threadIdx.x == 0)
+        __hip_atomic_store(&w.tile_flag[g.tbase + g.local], pl.epoch, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Pieces of the leaf-merge pipeline for one workgroup.
 template <typename K, typename V, int THREADS, int IPT>
 struct LeafOps {
@@ -257,27 +287,9 @@ struct LeafOps {
         __syncthreads();
     }
 
-    // Wait until every tile that reads this window has its inputs on chip.
-    // Flags are touched only with relaxed device-scope atomics: the readers'
-    // loads have returned before they publish, and an acquire/release fence
-    // at device scope would write back or invalidate this XCD's whole L2 on
-    // every poll.  Returns false if the bounded wait expired.
     static __device__ __forceinline__ bool wait_readers(const TileGeo &g, const Plan &pl,
                                                         const Work &w) {
-        if (g.ntiles <= 1) return true;
-        int bad = 0;
-        for (int q = g.wlo + (int)threadIdx.x; q <= g.whi && !bad; q += THREADS) {
-            if (q == g.local) continue;
-            const unsigned *f = &w.tile_flag[g.tbase + q];
-            unsigned spins = 0;
-            while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pl.epoch) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinLimit) { bad = 1; break; }
-            }
-        }
-        bad = __syncthreads_or(bad);
-        if (bad && threadIdx.x == 0) atomicOr(&w.ctr->error, kErrBarrierSpin);
-        return !bad;
+        return wait_window<THREADS>(g, pl, w);
     }
 
     // Coalesced store of the window from registers.
@@ -400,6 +412,220 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
             if (!leaf_step<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, rb, vb, ra, va)) break;
         }
     }
+}
+
+// ---- wide rows --------------------------------------------------------------
+// Leaf merge of rows of W bytes ordered by their leading key: the elements of
+// the paper's experiments (Sec. 4), a key followed by a payload.  Rows move
+// in chunks of CH = 16, 8 or 4 bytes (the largest that divides W); a thread
+// holds kRowChunks chunks of a tile, so a tile is R output rows with
+// R * W <= 512 * kRowChunks * CH (64, 32 or 16 KiB).  Per tile:
+//   1. the keys of its A- and B-slices go to LDS (one load per row);
+//   2. each thread merges four consecutive outputs (stable, ties take A) and
+//      records each output row's input row in LDS;
+//   3. the rows are gathered chunk by chunk straight into registers in
+//      output order: chunk c of the tile is chunk c of its output window;
+//   4. "inputs read" is published once every load has returned;
+//   5. after the readers of the window have published, a coalesced store.
+// Grid, slot order and reader ranges are those of k_leafmerge.  A workgroup
+// holds two tiles in registers, the one waiting to be stored and the next,
+// which it reads before it waits: the depth-2 argument above applies, so a
+// leaf may have 2G tiles.
+constexpr int kRowThreads = 512;
+constexpr int kRowChunks = 8;                              // per thread and tile
+constexpr int kRowMaxRows = 2048;
+constexpr int kRowOutsPerThread = kRowMaxRows / kRowThreads;
+
+template <int CH> struct ChunkT;
+template <> struct ChunkT<4> { typedef uint32_t type; };
+template <> struct ChunkT<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
+template <> struct ChunkT<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+
+template <int CH>
+__device__ __forceinline__ void chunk_store(typename ChunkT<CH>::type v, __amdgpu_buffer_rsrc_t r,
+                                            int off) {
+    if constexpr (CH == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+    else if constexpr (CH == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+    else __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+
+// Row shape of a call: bytes per row, chunks per row, rows per tile, and
+// for cpr >= 2 magic = floor(2^32 / cpr) + 1, so that c / cpr equals the
+// high word of c * magic for every chunk index c of a tile (c * cpr < 2^32).
+struct RowGeo {
+    int64_t W;
+    uint32_t magic;
+    int32_t cpr, R, pad;
+};
+
+template <typename K, int CH>
+struct RowOps {
+    typedef typename ChunkT<CH>::type C;
+    static constexpr int CPT = kRowChunks;
+
+    static __device__ __forceinline__ int64_t row_of(const TileGeo &g, int x) {
+        return x < g.na ? g.a0 + x : g.b0 + (x - g.na);
+    }
+
+    // Keys to LDS, then the byte offset of the source row of every output
+    // row of the tile into so.
+    static __device__ __forceinline__ void order(const unsigned char *data, const RowGeo &rg,
+                                                 const TileGeo &g, K *sk, int64_t *so) {
+        const int tid = threadIdx.x;
+        const int n = g.n, na = g.na, nb = g.n - g.na;
+        for (int x = tid; x < n; x += kRowThreads)
+            sk[x] = *reinterpret_cast<const K *>(data + row_of(g, x) * rg.W);
+        if (tid == 0) sk[n] = key_max<K>();   // B sentinel: an exhausted B never wins
+        __syncthreads();
+        const int d = tid * kRowOutsPerThread;
+        if (d < n) {
+            int lo = d > nb ? d - nb : 0;
+            int hi = d < na ? d : na;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sk[mid] <= sk[na + d - 1 - mid]) lo = mid + 1;
+                else hi = mid;
+            }
+            int ia = lo, bi = na + (d - lo);
+#pragma unroll
+            for (int e = 0; e < kRowOutsPerThread; ++e) {
+                if (d + e < n) {
+                    const bool ta = ia < na && sk[ia] <= sk[bi];
+                    so[d + e] = row_of(g, ta ? ia : bi) * rg.W;
+                    ia += ta ? 1 : 0;
+                    bi += ta ? 0 : 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Gather the tile into registers (output order), wait for the loads,
+    // publish "inputs read".  The LDS is free again on return.
+    static __device__ __forceinline__ void read(const unsigned char *data, const RowGeo &rg,
+                                                const TileGeo &g, K *sk, int64_t *so,
+                                                C (&r)[CPT], const Plan &pl, const Work &w) {
+        order(data, rg, g, sk, so);
+        const int nch = g.n * rg.cpr;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int c = (int)threadIdx.x + q * kRowThreads;
+            if (c < nch) {
+                const int o = rg.cpr == 1 ? c : (int)__umulhi((uint32_t)c, rg.magic);
+                const int part = c - o * rg.cpr;
+                r[q] = *reinterpret_cast<const C *>(data + so[o] + part * CH);
+            }
+        }
+        wait_dma();
+        __syncthreads();
+        publish_read(g, pl, w);
+    }
+
+    static __device__ __forceinline__ void store(unsigned char *data, const RowGeo &rg,
+                                                 const TileGeo &g, const C (&r)[CPT]) {
+        const int nch = g.n * rg.cpr;
+        const __amdgpu_buffer_rsrc_t ro = buf_rsrc(data + g.out0 * rg.W, (int64_t)nch * CH);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int c = (int)threadIdx.x + q * kRowThreads;
+            if (c < nch) chunk_store<CH>(r[q], ro, c * CH);
+        }
+    }
+};
+
+template <typename K, int CH>
+__device__ __forceinline__ bool row_step(unsigned char *data, const RowGeo &rg, const Plan &pl,
+                                         const Work &w, K *sk, int64_t *so, int64_t ntiles,
+                                         int64_t &t, TileGeo &g,
+                                         typename RowOps<K, CH>::C (&cur)[RowOps<K, CH>::CPT],
+                                         typename RowOps<K, CH>::C (&nxt)[RowOps<K, CH>::CPT]) {
+    const int64_t tn = t + gridDim.x;
+    const bool has = tn < ntiles;
+    TileGeo gn = g;
+    if (has) {
+        gn = tile_geo(w, tn, rg.R);
+        RowOps<K, CH>::read(data, rg, gn, sk, so, nxt, pl, w);
+    }
+    if (wait_window<kRowThreads>(g, pl, w)) RowOps<K, CH>::store(data, rg, g, cur);
+    if (!has) return false;
+    t = tn;
+    g = gn;
+    return true;
+}
+
+template <typename K, int CH>
+__global__ __launch_bounds__(kRowThreads, 4) void k_leafrows(unsigned char *__restrict__ data,
+                                                             RowGeo rg, Plan pl, Work w) {
+    using Ops = RowOps<K, CH>;
+    __shared__ K sk[kRowMaxRows + 1];
+    __shared__ int64_t so[kRowMaxRows];
+    int64_t ntiles = (int64_t)w.ctr->tiles;
+    if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    typename Ops::C ra[Ops::CPT], rb[Ops::CPT];
+    TileGeo g = tile_geo(w, t, rg.R);
+    Ops::read(data, rg, g, sk, so, ra, pl, w);
+    for (;;) {
+        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, ra, rb)) break;
+        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, rb, ra)) break;
+    }
+}
+
+template <typename K>
+static const void *rows_kernel_ch(int ch) {
+    switch (ch) {
+        case 4: return (const void *)&k_leafrows<K, 4>;
+        case 8: return (const void *)&k_leafrows<K, 8>;
+        case 16: return (const void *)&k_leafrows<K, 16>;
+    }
+    return nullptr;
+}
+
+static const void *rows_kernel(int key, int ch) {
+    switch (key) {
+        case kI32: return rows_kernel_ch<int32_t>(ch);
+        case kU32: return rows_kernel_ch<uint32_t>(ch);
+        case kI64: return rows_kernel_ch<int64_t>(ch);
+        case kU64: return rows_kernel_ch<uint64_t>(ch);
+    }
+    return nullptr;
+}
+
+int rows_tile(int64_t row_bytes, int ch) {
+    int64_t r = (int64_t)kRowThreads * kRowChunks * ch / row_bytes;
+    if (r > kRowMaxRows) r = kRowMaxRows;
+    return r < 1 ? 0 : (int)r;
+}
+
+int rows_grid(int key, int ch) {
+    const void *fn = rows_kernel(key, ch);
+    if (!fn) return 0;
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kRowThreads, 0) != hipSuccess)
+        return 0;
+    return per_cu < 1 ? 0 : per_cu * cus;
+}
+
+hipError_t launch_leafrows(int key, int ch, void *data, int64_t row_bytes, const Plan &pl,
+                           const Work &w, hipStream_t s) {
+    const void *fn = rows_kernel(key, ch);
+    const int R = rows_tile(row_bytes, ch);
+    if (!fn || R < 1 || row_bytes % ch != 0 || pl.tile != R) return hipErrorInvalidValue;
+    RowGeo rg;
+    rg.W = row_bytes;
+    rg.cpr = (int32_t)(row_bytes / ch);
+    rg.magic = rg.cpr >= 2 ? (uint32_t)((((uint64_t)1 << 32) / (uint64_t)rg.cpr) + 1) : 0u;
+    rg.R = R;
+    rg.pad = 0;
+    Plan plc = pl;
+    Work wc = w;
+    unsigned char *d = (unsigned char *)data;
+    void *args[] = {&d, &rg, &plc, &wc};
+    return hipLaunchCooperativeKernel(fn, dim3(pl.grid_leaf), dim3(kRowThreads), args, 0, s);
 }
 
 // ---- out-of-place merge (comparator) ---------------------------------------

@@ -15,9 +15,18 @@
 
 namespace imerge {
 
+// The searches read keys through `KP`: a plain pointer (packed keys), or
+// RowKeys (rows of several words ordered by their leading key).
 template <typename K>
-__device__ __forceinline__ int64_t corank_binary(const K *__restrict__ A, int64_t la,
-                                                 const K *__restrict__ B, int64_t lb,
+struct RowKeys {
+    const K *p;
+    int64_t s;            // row length in key units
+    __device__ __forceinline__ K operator[](int64_t m) const { return p[m * s]; }
+    __device__ __forceinline__ RowKeys operator+(int64_t m) const { return RowKeys{p + m * s, s}; }
+};
+
+template <typename KP>
+__device__ __forceinline__ int64_t corank_binary(KP A, int64_t la, KP B, int64_t lb,
                                                  int64_t k, int64_t lo, int64_t hi,
                                                  uint32_t &probes) {
     // Invariant: every m < lo has P(m) true, every m >= hi has P(m) false.
@@ -30,9 +39,8 @@ __device__ __forceinline__ int64_t corank_binary(const K *__restrict__ A, int64_
     return lo;
 }
 
-template <typename K>
-__device__ __forceinline__ int64_t corank_plain(const K *__restrict__ A, int64_t la,
-                                                const K *__restrict__ B, int64_t lb, int64_t k,
+template <typename KP>
+__device__ __forceinline__ int64_t corank_plain(KP A, int64_t la, KP B, int64_t lb, int64_t k,
                                                 uint32_t &probes) {
     int64_t lo = k > lb ? k - lb : 0;
     int64_t hi = k < la ? k : la;
@@ -46,16 +54,15 @@ __device__ __forceinline__ int64_t corank_plain(const K *__restrict__ A, int64_t
 // values are equal, that probe pair is the result (the printed listing tests
 // p_A, p_B before setting them and recomputes midpoints after such a stop).
 // One lane, sequential dependent probes.  `probes` counts value pairs read.
-template <typename K>
-__device__ __forceinline__ void find_median(const K *__restrict__ A, int64_t la,
-                                            const K *__restrict__ B, int64_t lb, int64_t &pa,
+template <typename KP>
+__device__ __forceinline__ void find_median(KP A, int64_t la, KP B, int64_t lb, int64_t &pa,
                                             int64_t &pb, uint32_t &probes) {
     if (la == 0 || lb == 0 || A[la - 1] <= B[0]) { pa = la; pb = 0; return; }
     if (!(A[0] <= B[lb - 1])) { pa = 0; pb = lb; return; }
     int64_t left_a = 0, limit_a = la, left_b = 0, limit_b = lb;
     pa = la / 2;
     pb = lb / 2;
-    K va = A[pa], vb = B[pb];
+    auto va = A[pa], vb = B[pb];
     ++probes;
     while (left_a < limit_a && left_b < limit_b && va != vb) {
         pa = (limit_a - left_a) / 2 + left_a;
@@ -92,9 +99,8 @@ __device__ __forceinline__ float mlp_eval(const MlpDev *__restrict__ M, float x)
 // Learned co-rank.  kg: global diagonal of the instance (size n_inst, A size
 // la_inst); i0: global co-rank of the start of the searched sub-problem
 // (A/B here are that sub-problem's parts), k: local diagonal.
-template <typename K>
-__device__ __forceinline__ int64_t corank_learned(const K *__restrict__ A, int64_t la,
-                                                  const K *__restrict__ B, int64_t lb, int64_t k,
+template <typename KP>
+__device__ __forceinline__ int64_t corank_learned(KP A, int64_t la, KP B, int64_t lb, int64_t k,
                                                   const MlpDev *__restrict__ M, int64_t kg,
                                                   int64_t n_inst, int64_t la_inst, int64_t i0,
                                                   uint32_t &probes) {
@@ -179,9 +185,8 @@ __device__ __forceinline__ int64_t group_search(int64_t lo, int64_t hi, Pred P, 
     return lo + __popcll((__ballot(p) >> gbase) & gmask);
 }
 
-template <int W, typename K>
-__device__ __forceinline__ int64_t corank_group(const K *__restrict__ A, int64_t la,
-                                                const K *__restrict__ B, int64_t lb, int64_t k,
+template <int W, typename KP>
+__device__ __forceinline__ int64_t corank_group(KP A, int64_t la, KP B, int64_t lb, int64_t k,
                                                 uint32_t &rounds) {
     const int64_t lo = k > lb ? k - lb : 0;
     const int64_t hi = k < la ? k : la;
@@ -191,9 +196,8 @@ __device__ __forceinline__ int64_t corank_group(const K *__restrict__ A, int64_t
 // Learned group co-rank: the first round probes W points spaced by the
 // model's typical error around its prediction, then the plain rounds go on
 // inside the bracket that round leaves (always exact).
-template <int W, typename K>
-__device__ __forceinline__ int64_t corank_group_learned(const K *__restrict__ A, int64_t la,
-                                                        const K *__restrict__ B, int64_t lb,
+template <int W, typename KP>
+__device__ __forceinline__ int64_t corank_group_learned(KP A, int64_t la, KP B, int64_t lb,
                                                         int64_t k, const MlpDev *__restrict__ M,
                                                         int64_t kg, int64_t n_inst,
                                                         int64_t la_inst, int64_t i0,

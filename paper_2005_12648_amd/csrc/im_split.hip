@@ -81,6 +81,12 @@ __device__ __forceinline__ void cs_shape(int64_t lx, int64_t ly, int64_t &g, int
 
 __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int level, int64_t pos,
                                          int64_t lx, int64_t ly) {
+    // counters count elements; the descriptor is in exchange units
+    const int64_t elems = lx + ly;
+    const bool three_rev = lx != ly;
+    pos *= pl.rot_scale;
+    lx *= pl.rot_scale;
+    ly *= pl.rot_scale;
     int64_t nw, stash0 = -1;
     if (pl.rot_method == kRotCS) {
         int64_t g, nseg;
@@ -121,9 +127,9 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
     r.c = 0;
     r.pad = 0;
     w.rot[slot] = r;
-    atomicAdd(&w.ctr->rotated, (unsigned long long)(lx + ly));
-    if (lx != ly && pl.rot_method != kRotCS) {
-        atomicAdd(&w.ctr->rotated_rev, (unsigned long long)(lx + ly));
+    atomicAdd(&w.ctr->rotated, (unsigned long long)elems);
+    if (three_rev && pl.rot_method != kRotCS) {
+        atomicAdd(&w.ctr->rotated_rev, (unsigned long long)elems);
         atomicAdd(&w.ctr->level_rev[level], 1ull);
     }
 }
@@ -291,7 +297,8 @@ __device__ __forceinline__ bool fz_emit_cycles(const Plan &pl, const Work &w, in
     const bool leader = moving && lane < n1 && (clen < 3 || lane < n2) && (clen < 4 || lane < n3);
     const int64_t s1 = __shfl(c, n1, 64), s2 = __shfl(c, n2, 64), s3 = __shfl(c, n3, 64);
     // inclusive scans of work items and cycles over the leader lanes
-    const int64_t nw = leader ? (L + kRotChunk - 1) / kRotChunk : 0;
+    const int64_t us = pl.rot_scale;            // descriptors are in exchange units
+    const int64_t nw = leader ? (L * us + kRotChunk - 1) / kRotChunk : 0;
     int64_t sw = nw, mv = leader ? (int64_t)clen * L : 0;
     int sc = leader ? 1 : 0;
 #pragma unroll
@@ -319,15 +326,15 @@ __device__ __forceinline__ bool fz_emit_cycles(const Plan &pl, const Work &w, in
     }
     if (leader) {
         Rot r;
-        r.pos = base; r.lx = 0; r.ly = 0;
+        r.pos = base * us; r.lx = 0; r.ly = 0;
         r.w0 = (int64_t)(packed & kRotWorkMask) + sw - nw;
         r.nw = nw;
         r.stash0 = -1;
-        r.len = L;
-        r.start[0] = base + c;
-        r.start[1] = base + s1;
-        r.start[2] = clen > 2 ? base + s2 : 0;
-        r.start[3] = clen > 3 ? base + s3 : 0;
+        r.len = L * us;
+        r.start[0] = (base + c) * us;
+        r.start[1] = (base + s1) * us;
+        r.start[2] = clen > 2 ? (base + s2) * us : 0;
+        r.start[3] = clen > 3 ? (base + s3) * us : 0;
         r.c = clen;
         r.pad = 0;
         w.rot[slot0 + sc - 1] = r;
@@ -358,8 +365,8 @@ __device__ __forceinline__ void emit_node(const Plan &pl, const Work &w, int lev
 // What a child of a fused node does at the next level, read on the original
 // layout: 0 = nothing to split (empty part, in order, or a leaf), 1 = a
 // symmetric split (block swap), 2 = anything else (not fusable).
-template <typename K>
-__device__ __forceinline__ int child_kind(const Plan &pl, const K *A, int64_t la, const K *B,
+template <typename KP>
+__device__ __forceinline__ int child_kind(const Plan &pl, KP A, int64_t la, KP B,
                                           int64_t lb) {
     if (la == 0 || lb == 0) return 0;
     if (A[la - 1] <= B[0]) return 0;
@@ -372,8 +379,8 @@ __device__ __forceinline__ int child_kind(const Plan &pl, const K *A, int64_t la
 // One lane per node classifies it (early exits, leaf); the nodes of a wave
 // that must be split are then searched one after another by the whole wave
 // with the cooperative 64-ary co-rank (a handful of dependent rounds).
-template <typename K, bool LEARNED>
-__global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ data,
+template <typename K, typename KP, bool LEARNED>
+__global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
                                                          const int64_t *__restrict__ offsets,
                                                          Plan pl, Work w, int level,
                                                          const MlpDev *__restrict__ mlp) {
@@ -399,8 +406,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
         if (idx < cnt) {
             nd = in[idx];
             const int64_t la = nd.la, lb = nd.lb;
-            const K *A = data + nd.base;
-            const K *B = A + la;
+            const KP A = data + nd.base;
+            const KP B = A + la;
             if (la == 0 || lb == 0) {
                 // nothing to merge
             } else if (A[la - 1] <= B[0]) {
@@ -445,8 +452,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(const K *__restrict__ d
             const int64_t la = __shfl(nd.la, src, 64);
             const int64_t lb = __shfl(nd.lb, src, 64);
             const int64_t kk = __shfl(k, src, 64);
-            const K *A = data + base;
-            const K *B = A + la;
+            const KP A = data + base;
+            const KP B = A + la;
             int64_t i;
             ++searches;
             if (LEARNED) {
@@ -616,8 +623,8 @@ hipError_t launch_divide(int key, const void *data, int64_t la, int64_t lb, int 
 // One lane per tile, binary searches.  (Measured: group-cooperative searches
 // with 8 lanes per tile need fewer dependent rounds but 2-3x the loads, and
 // are slower here: this stage is bound by the memory system, not latency.)
-template <typename K, bool LEARNED>
-__global__ __launch_bounds__(kSplitThreads) void k_tilerank(const K *__restrict__ data,
+template <typename K, typename KP, bool LEARNED>
+__global__ __launch_bounds__(kSplitThreads) void k_tilerank(KP data,
                                                             const int64_t *__restrict__ offsets,
                                                             Plan pl, Work w,
                                                             const MlpDev *__restrict__ mlp) {
@@ -638,8 +645,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_tilerank(const K *__restrict_
         const int64_t d = (t - w.tile_start[lo]) * pl.tile;
         int64_t i = 0;
         if (d > 0) {
-            const K *A = data + lf.base;
-            const K *B = A + lf.la;
+            const KP A = data + lf.base;
+            const KP B = A + lf.la;
             ++searches;
             if (LEARNED) {
                 int64_t o0 = offsets[2 * lf.inst], o1 = offsets[2 * lf.inst + 1],
@@ -689,7 +696,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_corank(const K *__restrict__ 
 // Checked mode: every run ascending, every instance's offsets monotone.
 template <typename K>
 __global__ void k_check_sorted(const K *__restrict__ data, const int64_t *__restrict__ offsets,
-                               int64_t n_inst, Counters *ctr) {
+                               int64_t n_inst, Counters *ctr, int64_t stride) {
     for (int64_t q = blockIdx.x; q < n_inst; q += gridDim.x) {
         int64_t o0 = offsets[2 * q], o1 = offsets[2 * q + 1], o2 = offsets[2 * q + 2];
         if (o1 < o0 || o2 < o1) {
@@ -699,7 +706,7 @@ __global__ void k_check_sorted(const K *__restrict__ data, const int64_t *__rest
         bool bad = false;
         for (int64_t x = o0 + threadIdx.x; x + 1 < o2; x += blockDim.x) {
             if (x + 1 == o1) continue;                       // the A|B seam is not a run
-            if (data[x + 1] < data[x]) bad = true;
+            if (data[(x + 1) * stride] < data[x * stride]) bad = true;
         }
         if (bad) atomicOr(&ctr->error, kErrNotSorted);
     }
@@ -725,12 +732,17 @@ template <typename K>
 static hipError_t split_t(const void *data, const int64_t *offs, const Plan &pl, const Work &w,
                           int level, const MlpDev *mlp, hipStream_t s) {
     int g = grid_for(pl.cap_nodes, kSplitThreads, 2048);
-    if (mlp)
-        hipLaunchKernelGGL((k_split<K, true>), dim3(g), dim3(kSplitThreads), 0, s,
+    if (pl.row_stride > 0) {
+        if (mlp) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_split<K, RowKeys<K>, false>), dim3(g), dim3(kSplitThreads), 0, s,
+                           RowKeys<K>{(const K *)data, pl.row_stride}, offs, pl, w, level, mlp);
+    } else if (mlp) {
+        hipLaunchKernelGGL((k_split<K, const K *, true>), dim3(g), dim3(kSplitThreads), 0, s,
                            (const K *)data, offs, pl, w, level, mlp);
-    else
-        hipLaunchKernelGGL((k_split<K, false>), dim3(g), dim3(kSplitThreads), 0, s,
+    } else {
+        hipLaunchKernelGGL((k_split<K, const K *, false>), dim3(g), dim3(kSplitThreads), 0, s,
                            (const K *)data, offs, pl, w, level, mlp);
+    }
     return hipGetLastError();
 }
 
@@ -749,12 +761,17 @@ template <typename K>
 static hipError_t tilerank_t(const void *data, const int64_t *offs, const Plan &pl, const Work &w,
                              const MlpDev *mlp, hipStream_t s) {
     int g = grid_for(pl.cap_tiles, kSplitThreads, 4096);
-    if (mlp)
-        hipLaunchKernelGGL((k_tilerank<K, true>), dim3(g), dim3(kSplitThreads), 0, s,
+    if (pl.row_stride > 0) {
+        if (mlp) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tilerank<K, RowKeys<K>, false>), dim3(g), dim3(kSplitThreads), 0, s,
+                           RowKeys<K>{(const K *)data, pl.row_stride}, offs, pl, w, mlp);
+    } else if (mlp) {
+        hipLaunchKernelGGL((k_tilerank<K, const K *, true>), dim3(g), dim3(kSplitThreads), 0, s,
                            (const K *)data, offs, pl, w, mlp);
-    else
-        hipLaunchKernelGGL((k_tilerank<K, false>), dim3(g), dim3(kSplitThreads), 0, s,
+    } else {
+        hipLaunchKernelGGL((k_tilerank<K, const K *, false>), dim3(g), dim3(kSplitThreads), 0, s,
                            (const K *)data, offs, pl, w, mlp);
+    }
     return hipGetLastError();
 }
 
@@ -795,24 +812,24 @@ hipError_t launch_corank(int key, const void *data, int64_t la, int64_t lb, cons
 }
 
 hipError_t launch_check_sorted(int key, const void *data, const int64_t *d_offsets,
-                               int64_t n_inst, Counters *ctr, hipStream_t s) {
+                               int64_t n_inst, Counters *ctr, int64_t stride, hipStream_t s) {
     int g = (int)(n_inst < 4096 ? (n_inst < 1 ? 1 : n_inst) : 4096);
     switch (key) {
         case kI32:
             hipLaunchKernelGGL(k_check_sorted<int32_t>, dim3(g), dim3(256), 0, s,
-                               (const int32_t *)data, d_offsets, n_inst, ctr);
+                               (const int32_t *)data, d_offsets, n_inst, ctr, stride);
             break;
         case kU32:
             hipLaunchKernelGGL(k_check_sorted<uint32_t>, dim3(g), dim3(256), 0, s,
-                               (const uint32_t *)data, d_offsets, n_inst, ctr);
+                               (const uint32_t *)data, d_offsets, n_inst, ctr, stride);
             break;
         case kI64:
             hipLaunchKernelGGL(k_check_sorted<int64_t>, dim3(g), dim3(256), 0, s,
-                               (const int64_t *)data, d_offsets, n_inst, ctr);
+                               (const int64_t *)data, d_offsets, n_inst, ctr, stride);
             break;
         case kU64:
             hipLaunchKernelGGL(k_check_sorted<uint64_t>, dim3(g), dim3(256), 0, s,
-                               (const uint64_t *)data, d_offsets, n_inst, ctr);
+                               (const uint64_t *)data, d_offsets, n_inst, ctr, stride);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -1,0 +1,158 @@
+"""Wide rows (the elements of the paper's Sec. 4 test cases: a key in the
+first word, then a payload) merged in place on the GPU, against the CPU
+oracle's stable row merge, row by row and word by word.
+
+* row widths that select each chunk width of the rows leaf merge (16, 8 and
+  4 bytes) and rows from one key word to 64 KiB, with ragged last tiles;
+* all four key types, ties, skewed sizes, already ordered and inverted runs;
+* small leaf capacities (IM_LEAF_TILES) so the division runs several
+  levels, with the fused two-level exchange on and off (IM_FUSE=0), and a
+  small grid (IM_LEAF_GRID) so tiles wait for their readers.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+import paper_2005_12648_amd as im
+
+pytestmark = pytest.mark.gpu
+
+TDT = {np.int32: torch.int32, np.uint32: torch.uint32, np.int64: torch.int64,
+       np.uint64: torch.uint64}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def d(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def h(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture
+def env(monkeypatch):
+    def setter(tiles=None, fuse=True, grid=None):
+        for k, v in (("IM_LEAF_TILES", tiles), ("IM_LEAF_GRID", grid)):
+            if v is None:
+                monkeypatch.delenv(k, raising=False)
+            else:
+                monkeypatch.setenv(k, str(v))
+        if fuse:
+            monkeypatch.delenv("IM_FUSE", raising=False)
+        else:
+            monkeypatch.setenv("IM_FUSE", "0")
+    return setter
+
+
+def run(rows, la, dev):
+    t = d(rows, dev)
+    im.inplace_merge_rows(t, la)
+    st = im.fetch_stats()
+    got = h(t)
+    want = oracle.merge_rows(rows, la)
+    bad = np.flatnonzero(np.any(got != want, axis=1))
+    return bad, st
+
+
+# (row bytes, rows in A, rows in B): chunk 16 / 8 / 4 bytes, ragged tiles
+SHAPES = [(4, 70001, 65537), (8, 40000, 50003), (12, 30001, 29999), (16, 25000, 27001),
+          (20, 20011, 19999), (64, 9001, 12007), (100, 5003, 4001), (256, 3001, 2999),
+          (1000, 1201, 999), (4096, 301, 277), (16384, 77, 91), (65536, 23, 19)]
+
+
+@pytest.mark.parametrize("row_bytes,la,lb", SHAPES)
+def test_rows_shapes(dev, env, row_bytes, la, lb):
+    env(tiles=2)
+    rows = gen.rows_pair(la, lb, row_bytes // 4, 100 + row_bytes)
+    say("rows", row_bytes, la, lb)
+    bad, st = run(rows, la, dev)
+    assert bad.size == 0, "%d rows differ, first %d" % (bad.size, bad[0])
+    # (with one-row tiles and a two-tile leaf capacity every node ends in an
+    # early exit or a whole exchange, and no leaf is left to merge)
+    assert st["leaf_elems"] + st["rotated_elems"] > 0
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.uint32, np.int64, np.uint64])
+def test_rows_key_types_and_ties(dev, env, dt):
+    env(tiles=3)
+    for la, lb, hi, words in [(20000, 23001, 2 ** 31, 16), (15000, 15000, 7, 8),
+                              (300, 40000, 2 ** 31, 4), (40000, 300, 1000, 32)]:
+        keys = gen.pair_uniform(la, lb, 7 + la, hi=hi, dtype=dt)
+        rows = gen.rows_pair(la, lb, words, 9 + lb, dtype=dt, keys=keys)
+        say("rows", dt.__name__, la, lb, hi, words)
+        t = torch.from_numpy(rows).to(dev)
+        assert t.dtype == TDT[dt]
+        im.inplace_merge_rows(t, la)
+        want = oracle.merge_rows(rows, la)
+        assert np.array_equal(h(t), want), (la, lb, hi)
+
+
+@pytest.mark.parametrize("tiles", [1, 2, 5])
+@pytest.mark.parametrize("fuse", [True, False])
+def test_rows_division_levels(dev, env, tiles, fuse):
+    env(tiles=tiles, fuse=fuse)
+    for row_bytes, la, lb, seed in [(64, 60000, 60000, 1), (48, 50001, 70003, 2),
+                                    (512, 8000, 9000, 3)]:
+        rows = gen.rows_pair(la, lb, row_bytes // 4, seed)
+        say("levels", tiles, fuse, row_bytes, la, lb)
+        bad, st = run(rows, la, dev)
+        assert bad.size == 0, "%d rows differ" % bad.size
+        assert st["levels_used"] >= 2
+        if not fuse:
+            assert st["fused_nodes"] == 0
+
+
+def test_rows_small_grid_waits(dev, env):
+    # a grid of 3 workgroups: every tile of a leaf waits for its readers
+    env(tiles=None, grid=3)
+    for row_bytes, la, lb in [(64, 20000, 21001), (1024, 1500, 1400), (12, 40001, 39999)]:
+        rows = gen.rows_pair(la, lb, row_bytes // 4, 31 + la)
+        say("grid 3", row_bytes, la, lb)
+        bad, _ = run(rows, la, dev)
+        assert bad.size == 0
+
+
+def test_rows_special_cases(dev, env):
+    env(tiles=2)
+    w = 16
+    # already ordered, inverted (a single exchange B|A), all keys equal
+    a = gen.rows_pair(5000, 0, w, 41)
+    b = gen.rows_pair(4000, 0, w, 42)
+    b[:, 0] += a[-1, 0]
+    ordered = np.concatenate([a, b])
+    inverted = np.concatenate([b, a])
+    same = gen.rows_pair(6000, 7000, w, 43)
+    same[:, 0] = 5
+    for label, rows, la in [("ordered", ordered, 5000), ("inverted", inverted, 4000),
+                            ("equal", same, 6000)]:
+        say("special", label)
+        bad, _ = run(rows, la, dev)
+        assert bad.size == 0, label
+    assert np.array_equal(oracle.merge_rows(same, 6000), same)
+    # one side empty: nothing happens
+    t = d(ordered, dev)
+    im.inplace_merge_rows(t, 0)
+    im.inplace_merge_rows(t, t.shape[0])
+    assert np.array_equal(h(t), ordered)
+
+
+def test_rows_paper_generator(dev, env):
+    # the paper's W1 keys (Sec. 4) with 1 KiB elements, split at 1/4, 1/2, 3/4
+    env()
+    for frac, seed in ((0.25, 51), (0.5, 52), (0.75, 53)):
+        n = 24000
+        keys = gen.paper_w1_pair(n, frac, seed)
+        la = int(n * frac)
+        rows = gen.rows_pair(la, n - la, 256, seed, keys=keys)
+        say("w1 rows", frac)
+        bad, _ = run(rows, la, dev)
+        assert bad.size == 0

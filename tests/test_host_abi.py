@@ -116,3 +116,21 @@ def test_no_oracle_in_product_path():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt, f
+
+
+def test_rows_validation_without_device_work():
+    lib = im.load()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    assert lib.inplace_merge_rows(fake, 4, 4, 64, 9, None) == -2            # dtype
+    assert lib.inplace_merge_rows(fake, -1, 4, 64, 0, None) == -1
+    assert lib.inplace_merge_rows(None, 4, 4, 64, 0, None) == -1
+    assert lib.inplace_merge_rows(fake, 4, 4, 0, 0, None) == -1             # row bytes
+    assert lib.inplace_merge_rows(fake, 4, 4, 6, 0, None) == -1             # not a multiple of 4
+    assert lib.inplace_merge_rows(fake, 4, 4, 12, 2, None) == -1            # 8-byte key
+    assert lib.inplace_merge_rows(fake, 4, 4, 65552, 0, None) == -1         # too wide
+    assert "too large" in _err(lib)
+    assert lib.inplace_merge_rows(fake, 4, 4, 20004, 0, None) == -1         # 4-byte chunks
+    assert lib.inplace_merge_rows(ctypes.c_void_p(0x1002), 4, 4, 64, 0, None) == -1   # alignment
+    assert lib.inplace_merge_rows(fake, 0, 9, 64, 0, None) == 0             # nothing to merge
+    assert lib.inplace_merge_rows_workspace_bytes(-1, 64, 0) == 0
+    assert lib.inplace_merge_rows_workspace_bytes(100, 0, 0) == 0

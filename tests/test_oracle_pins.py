@@ -337,3 +337,27 @@ def test_merge_par_equals_merge():
         got, threads = oracle.merge_par(d, la)
         assert threads >= 1
         assert np.array_equal(got, oracle.merge(d, la))
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.uint32, np.int64, np.uint64])
+def test_merge_rows_brute(dt):
+    # wide elements (Sec. 4: the key is the first word of each element): the
+    # stable merge of rows by their first column, by brute force; payload
+    # words must travel with their key
+    rng = np.random.default_rng(17)
+    for _ in range(200):
+        la, lb = (int(x) for x in rng.integers(0, 25, size=2))
+        w = int(rng.integers(1, 6))
+        a = np.sort(rng.integers(0, 5, la)).astype(dt)
+        b = np.sort(rng.integers(0, 5, lb)).astype(dt)
+        rows = rng.integers(0, 1000, size=(la + lb, w)).astype(dt)
+        rows[:, 0] = np.concatenate([a, b])
+        got = oracle.merge_rows(rows, la)
+        ref = brute_merge(a, b)
+        want = np.array([rows[t[2] + (0 if t[1] == 0 else la)] for t in ref],
+                        dtype=dt).reshape(la + lb, w)
+        assert np.array_equal(got, want)
+    # the input is not modified; a single column is the plain merge
+    x = np.array([[3], [7], [1], [9]], dtype=dt)
+    assert np.array_equal(oracle.merge_rows(x, 2)[:, 0], oracle.merge(x[:, 0].copy(), 2))
+    assert x[:, 0].tolist() == [3, 7, 1, 9]
