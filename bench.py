@@ -12,7 +12,8 @@ the dominant kernel (per-stage HIP events recorded on the merge's stream over
 the timed region), the CPU oracle timed on this host's cores, and the other
 forms side by side (batched merge of 4096 instances vs 4096 plain calls,
 in-place merge sort of 2^28 int32, learned split vs plain on int64 2^28+2^28,
-key+payload, skewed and duplicate-heavy variants).  Every GPU result is
+key+payload, skewed and duplicate-heavy variants, the paper's FindMedian and
+circular shifting, out-of-place comparators, and rows of 64 B to 64 KiB).  Every GPU result is
 compared with the CPU oracle; mismatch counts are part of the line.
 Progress goes to stderr.
 """
@@ -475,6 +476,51 @@ def bench_exchanges(torch, im, oracle, gen, dev, steps):
             "exchange": out, "merge_c2": merges}
 
 
+def bench_rows(torch, im, oracle, gen, dev, steps):
+    """f4: wide rows (Sec. 4 elements: key word + payload), 1 GiB per width,
+    L_A = L_B, uniform keys; against a plain device copy of the same bytes
+    (the floor of any method that moves every row once) and the oracle."""
+    out = {}
+    total = 2 ** 30
+    for W in (64, 256, 1024, 4096, 16384, 65536):
+        n = total // W
+        la = n // 2
+        log("f4: rows of %d bytes, %d + %d" % (W, la, n - la))
+        pristine = gen.torch_rows_pair(la, n - la, W // 4, SEED + 60 + W.bit_length(), dev)
+        buf = torch.empty_like(pristine)
+        ms = event_timed(torch, pristine, buf, lambda: im.inplace_merge_rows(buf, la), steps)
+        st = im.fetch_stats()
+        copy_ms = event_timed(torch, pristine, buf, lambda: buf.copy_(pristine), steps)
+        # stage split of one more merge (events on the merge's stream)
+        buf.copy_(pristine)
+        torch.cuda.synchronize()
+        im.profile_read()
+        im.profile(True)
+        im.inplace_merge_rows(buf, la)
+        torch.cuda.synchronize()
+        prof = im.profile_read()
+        im.profile(False)
+        want = oracle.merge_rows(pristine.cpu().numpy(), la)
+        got = buf.cpu().numpy()
+        bad = int(np.count_nonzero(np.any(got != want, axis=1)))
+        del got, want
+        moved = 2 * W * (st["rotated_elems"] + st["leaf_elems"])     # read + write
+        out["rows_%d_B" % W] = {
+            "rows": n, "ms": round(ms, 4), "grows_s": round(n / ms / 1e6, 4),
+            "effective_gb_s": round(2 * total / ms / 1e6, 1),
+            "copy_ms": round(copy_ms, 4), "copy_gb_s": round(2 * total / copy_ms / 1e6, 1),
+            "moved_bytes": moved, "moved_gb_s": round(moved / ms / 1e6, 1),
+            "levels_used": st["levels_used"], "leaves": st["leaves"],
+            "fused_nodes": st["fused_nodes"], "tile_rows": st["tile"],
+            "leaf_grid": st["leaf_grid"],
+            "stages_ms": {k: round(v[0], 4) for k, v in prof.items()},
+            "mismatched_rows": bad}
+        del pristine, buf
+        torch.cuda.empty_cache()
+    return {"workload": "rows of W bytes (int32 key + payload), 2^30/W rows, L_A = L_B, "
+                        "keys uniform in [0,2^31)", "widths": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -533,6 +579,8 @@ def main():
         forms["f2_findmedian"] = bench_findmedian(torch, im, gen, dev, 3)
         torch.cuda.empty_cache()
         forms["f3_exchange_and_out_of_place"] = bench_exchanges(torch, im, oracle, gen, dev, 3)
+        torch.cuda.empty_cache()
+        forms["f4_wide_rows"] = bench_rows(torch, im, oracle, gen, dev, 3)
     st = head["stats"]
     line = {
         "metric": "Gelem/s, in-place merge of int32 L_A=L_B=2^27",
