@@ -528,7 +528,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--forms", choices=["all", "none"], default="all")
+    ap.add_argument("--forms", choices=["all", "none", "rows"], default="all",
+                    help="other workloads after the headline: all, none, or only the rows form")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (profiling runs: default leaf configuration)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -580,6 +581,8 @@ def main():
         torch.cuda.empty_cache()
         forms["f3_exchange_and_out_of_place"] = bench_exchanges(torch, im, oracle, gen, dev, 3)
         torch.cuda.empty_cache()
+        forms["f4_wide_rows"] = bench_rows(torch, im, oracle, gen, dev, 3)
+    elif args.forms == "rows":
         forms["f4_wide_rows"] = bench_rows(torch, im, oracle, gen, dev, 3)
     st = head["stats"]
     line = {
