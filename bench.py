@@ -69,6 +69,28 @@ def traffic_from_profile(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def measured_hbm(ms: float):
+    """HBM bytes of one headline merge as rocprofv3 counted them (FETCH_SIZE +
+    WRITE_SIZE of the exchange and leaf-merge kernels, scaled by a plain copy
+    of known size), over the merge time; None unless both counter summaries
+    match the current kernel sources.  The split and co-rank kernels are left
+    out (latency-bound searches, a few MB)."""
+    total = 0.0
+    for kernel in ("rotate", "leafmerge"):
+        path = os.path.join(ROOT, "profiles", "traffic_%s_c2.json" % kernel)
+        per = traffic_from_profile(kernel, "c2")
+        if per is None:
+            return None
+        with open(path) as f:
+            rec = json.load(f)
+        total += rec["hbm_read_bytes_per_run"] + rec["hbm_write_bytes_per_run"]
+    gbs = total / ms / 1e6
+    return {"bytes_per_merge": int(total), "gb_s": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_elem": round(total / 2 ** 28, 2),
+            "source": "profiles/traffic_rotate_c2.json + profiles/traffic_leafmerge_c2.json"}
+
+
 class Timer:
     def __init__(self, torch):
         self.torch = torch
@@ -623,6 +645,7 @@ def main():
                    "autotune_ms_per_config": head["tune_ms"]},
         "effective_hbm_gb_s": round(2 * 4 * n / head["ms"] / 1e6, 1),
         "effective_hbm_frac": round(2 * 4 * n / head["ms"] / 1e6 / HBM_PEAK_GBS, 4),
+        "measured_hbm": measured_hbm(head["ms"]),
         "mismatches": head.get("mismatch"),
         "roofline": roof,
         "cpu_baseline": head["cpu"],
