@@ -197,9 +197,9 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->cap_stash = 2 * (total / kCsSeg) + 16;
     // Two division levels are fused into one exchange where the splits are
     // symmetric (k_split); the rotation kernel cycles up to kMaxCyc pieces
-    // only for elements of at most 8 bytes.  IM_FUSE=0 turns it off.
+    // only for elements of at most 12 bytes.  IM_FUSE=0 turns it off.
     const char *fz = std::getenv("IM_FUSE");
-    pl->fuse = (ek + ev <= 8 && !(fz && fz[0] == '0')) ? 1 : 0;
+    pl->fuse = (ek + ev <= 12 && !(fz && fz[0] == '0')) ? 1 : 0;
     pl->pad2 = 0;
     pl->row_stride = 0;
     pl->rot_scale = 1;

@@ -34,7 +34,7 @@ template <> struct ValBytes<NoVal> { static constexpr int v = 0; };
 template <int BYTES>
 struct RotGeom {
     static constexpr int threads = BYTES <= 4 ? 512 : 1024;
-    static constexpr int maxc = BYTES <= 8 ? kMaxCyc : 2;
+    static constexpr int maxc = BYTES <= 12 ? kMaxCyc : 2;
     static constexpr int per = (int)(kRotChunk / threads);
 };
 
