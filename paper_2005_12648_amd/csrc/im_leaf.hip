@@ -724,44 +724,55 @@ hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int6
 constexpr int kPlanThreads = 1024;
 
 __global__ __launch_bounds__(kPlanThreads) void k_plan(Plan pl, Work w) {
-    __shared__ long long buf[kPlanThreads];
-    __shared__ long long s_run;
+    constexpr int kWaves = kPlanThreads / 64;
+    __shared__ long long s_wave[kWaves];
     __shared__ unsigned long long s_elems;
     int64_t L = (int64_t)w.ctr->leaves;
     if (L > pl.cap_leaves) L = pl.cap_leaves;
-    const int tid = threadIdx.x;
-    unsigned long long my_elems = 0;
-    if (tid == 0) { s_run = 0; s_elems = 0; }
-    __syncthreads();
-    for (int64_t base = 0; base < L; base += kPlanThreads) {
-        int64_t l = base + tid;
-        long long c = 0;
-        if (l < L) {
-            int64_t S = w.leaves[l].la + w.leaves[l].lb;
-            my_elems += (unsigned long long)S;
-            c = (S + pl.tile - 1) / pl.tile;
-            w.leaves[l].ntiles = (int32_t)c;
-        }
-        buf[tid] = c;
-        __syncthreads();
-        // Hillis-Steele inclusive scan
-        for (int off = 1; off < kPlanThreads; off <<= 1) {
-            long long v = tid >= off ? buf[tid - off] : 0;
-            __syncthreads();
-            buf[tid] += v;
-            __syncthreads();
-        }
-        long long run = s_run;
-        if (l < L) w.tile_start[l] = run + buf[tid] - c;
-        __syncthreads();
-        if (tid == kPlanThreads - 1) s_run = run + buf[tid];
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) s_elems = 0;
+    // each thread owns a contiguous run of leaves: tile counts and their sum
+    const int64_t per = (L + kPlanThreads - 1) / kPlanThreads;
+    const int64_t l0 = (int64_t)tid * per < L ? (int64_t)tid * per : L;
+    const int64_t l1 = l0 + per < L ? l0 + per : L;
+    long long sum = 0;
+    unsigned long long elems = 0;
+    for (int64_t l = l0; l < l1; ++l) {
+        const int64_t S = w.leaves[l].la + w.leaves[l].lb;
+        const long long c = (S + pl.tile - 1) / pl.tile;
+        w.leaves[l].ntiles = (int32_t)c;
+        elems += (unsigned long long)S;
+        sum += c;
     }
-    if (my_elems) atomicAdd(&s_elems, my_elems);
+    // block-wide inclusive scan of the sums: in each wave, then of the waves
+    long long x = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl(x, lane >= off ? lane - off : 0, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        long long v = lane < kWaves ? s_wave[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < kWaves; off <<= 1) {
+            const long long y = __shfl(v, lane >= off ? lane - off : 0, 64);
+            if (lane >= off) v += y;
+        }
+        if (lane < kWaves) s_wave[lane] = v;
+    }
+    __syncthreads();
+    long long start = (x - sum) + (wid > 0 ? s_wave[wid - 1] : 0);
+    for (int64_t l = l0; l < l1; ++l) {
+        w.tile_start[l] = start;
+        start += w.leaves[l].ntiles;
+    }
+    if (elems) atomicAdd(&s_elems, elems);
     __syncthreads();
     if (tid == 0) {
         w.ctr->leaf_elems = s_elems;
-        long long tot = s_run;
+        long long tot = s_wave[kWaves - 1];
         if (tot > pl.cap_tiles) {
             atomicOr(&w.ctr->error, kErrCapacity);
             tot = pl.cap_tiles;
