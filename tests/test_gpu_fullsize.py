@@ -1,6 +1,8 @@
 """Full-size parity: the workloads of the benchmark at their full sizes, run
 through the C ABI in the launch configuration bench.py times, compared with
-the CPU oracle element by element (the oracle finishes each in seconds)."""
+the CPU oracle element by element (the oracle finishes each in seconds):
+c2 (plain, skewed, duplicate-heavy), c3 key+payload, the c4 batch and sort,
+c5 plain and learned, and 1 GiB of rows of 64 B, 4 KiB and 64 KiB."""
 import sys
 
 import numpy as np
@@ -84,3 +86,20 @@ def test_c5_plain_and_learned_full(dev):
     model.merge(t, la)
     torch.cuda.synchronize()
     assert int(np.count_nonzero(t.cpu().numpy() != want)) == 0
+
+
+@pytest.mark.parametrize("row_bytes", [64, 4096, 65536])
+def test_rows_full(dev, row_bytes):
+    # the rows form of the benchmark: 1 GiB of rows, L_A = L_B
+    n = 2 ** 30 // row_bytes
+    la = n // 2
+    rows = gen.rows_pair(la, n - la, row_bytes // 4, 12648 + 60 + row_bytes.bit_length())
+    say("full-size rows", row_bytes, n)
+    t = torch.from_numpy(rows).to(dev)
+    im.inplace_merge_rows(t, la)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    del t
+    want = oracle.merge_rows(rows, la)
+    bad = int(np.count_nonzero(np.any(got != want, axis=1)))
+    assert bad == 0, "rows %d: %d mismatched rows" % (row_bytes, bad)

@@ -156,3 +156,35 @@ def test_rows_paper_generator(dev, env):
         say("w1 rows", frac)
         bad, _ = run(rows, la, dev)
         assert bad.size == 0
+
+
+def test_rows_checked_mode_and_workspace(dev, env, monkeypatch):
+    env(tiles=2)
+    # checked mode reads the keys a row apart: an unsorted B is refused and
+    # nothing is merged; sorted runs pass
+    rows = gen.rows_pair(3000, 2000, 16, 61)
+    bad = rows.copy()
+    bad[3000:, 0] = bad[3000:, 0][::-1].copy()
+    monkeypatch.setenv("IM_CHECK", "1")
+    t = d(bad, dev)
+    with pytest.raises(im.IMError) as e:
+        im.inplace_merge_rows(t, 3000)
+    assert e.value.code == -5
+    bad_run, _ = run(rows, 3000, dev)
+    assert bad_run.size == 0
+    monkeypatch.delenv("IM_CHECK")
+    # a caller workspace sized by the rows query works; a 4 KiB one is refused
+    need = im.rows_workspace_bytes(rows.shape[0], 64, torch.int32)
+    assert need > 4096
+    buf = torch.empty(need, dtype=torch.uint8, device=dev)
+    im.set_workspace(buf)
+    try:
+        bad_ws, _ = run(rows, 3000, dev)
+        assert bad_ws.size == 0
+        small = torch.empty(4096, dtype=torch.uint8, device=dev)
+        im.set_workspace(small)
+        with pytest.raises(im.IMError) as e:
+            im.inplace_merge_rows(d(rows, dev), 3000)
+        assert e.value.code == -4
+    finally:
+        im.set_workspace(None)
