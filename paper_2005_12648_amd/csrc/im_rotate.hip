@@ -28,7 +28,7 @@ template <> struct ValBytes<NoVal> { static constexpr int v = 0; };
 
 // Per element width (key + payload bytes): threads per workgroup, the most
 // pieces an item may cycle (fused two-level exchanges need up to kMaxCyc;
-// wider elements run only pairs, and their levels are not fused), and the
+// 16-byte elements run only pairs, and their levels are not fused), and the
 // elements per thread and piece.  Every lane holds MAXC x PER elements per
 // item, twice (software pipeline).
 template <int BYTES>
@@ -420,8 +420,14 @@ hipError_t launch_rotate_cs_single(void *data, int64_t lx, int64_t ly, int esize
 template <typename EK, typename EV>
 static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, int level,
                         int phase, hipStream_t s) {
-    const int g = 2048;
+    // Persistent grid several times larger than the chip holds at once:
+    // workgroups that finish early are replaced, which balances the items.
+    // (Measured on the exchange stage of 2^28-element merges, grids of
+    // 768 ... 16384: exactly the resident workgroups is 6-13% slower than
+    // 2048; 6144 is best for 512-thread workgroups (int32: -6% against
+    // 2048), 4096 for 1024-thread ones (int64, key+payload: -3 to -5%).)
     constexpr int TH = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>::threads;
+    const int g = TH == 512 ? 6144 : 4096;
     hipLaunchKernelGGL((k_rotate<EK, EV>), dim3(g), dim3(TH), 0, s, (EK *)keys, (EV *)vals,
                        w.rot, w.ctr, pl.cap_rot, level, phase);
     return hipGetLastError();
