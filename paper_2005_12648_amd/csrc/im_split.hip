@@ -398,8 +398,14 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
     if (gid == 0 && cnt > 0) atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
     uint32_t rounds = 0, searches = 0;          // wave-uniform counts
     uint32_t fm_probes = 0, fm_searches = 0;    // per lane (FindMedian)
-    for (int64_t idx0 = gid - lane; idx0 < cnt; idx0 += stride) {   // wave-uniform
-        const int64_t idx = idx0 + lane;
+    // A level with no more nodes than waves gives each wave one node (lane
+    // 0), so their searches run side by side instead of one after another in
+    // one wave; otherwise a wave takes 64 consecutive nodes, one per lane.
+    const int64_t wave = gid >> 6, nwaves = stride >> 6;
+    const bool spread = cnt <= nwaves;
+    for (int64_t idx0 = spread ? wave : gid - lane; idx0 < cnt;
+         idx0 += spread ? cnt : stride) {                          // wave-uniform
+        const int64_t idx = spread ? (lane == 0 ? idx0 : cnt) : idx0 + lane;
         Node nd;
         bool split = false;
         int64_t k = 0;
@@ -731,16 +737,21 @@ hipError_t launch_init(const Plan &pl, const Work &w, const int64_t *d_offsets, 
 template <typename K>
 static hipError_t split_t(const void *data, const int64_t *offs, const Plan &pl, const Work &w,
                           int level, const MlpDev *mlp, hipStream_t s) {
-    int g = grid_for(pl.cap_nodes, kSplitThreads, 2048);
+    // few nodes: one-wave workgroups, one per possible node (up to 2048),
+    // so the waves' searches run side by side on different CUs
+    const bool few = pl.cap_nodes <= 128 * kSplitThreads;
+    const int th = few ? 64 : kSplitThreads;
+    const int g = few ? (int)(pl.cap_nodes < 2048 ? pl.cap_nodes : 2048)
+                      : grid_for(pl.cap_nodes, th, 2048);
     if (pl.row_stride > 0) {
         if (mlp) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_split<K, RowKeys<K>, false>), dim3(g), dim3(kSplitThreads), 0, s,
+        hipLaunchKernelGGL((k_split<K, RowKeys<K>, false>), dim3(g), dim3(th), 0, s,
                            RowKeys<K>{(const K *)data, pl.row_stride}, offs, pl, w, level, mlp);
     } else if (mlp) {
-        hipLaunchKernelGGL((k_split<K, const K *, true>), dim3(g), dim3(kSplitThreads), 0, s,
+        hipLaunchKernelGGL((k_split<K, const K *, true>), dim3(g), dim3(th), 0, s,
                            (const K *)data, offs, pl, w, level, mlp);
     } else {
-        hipLaunchKernelGGL((k_split<K, const K *, false>), dim3(g), dim3(kSplitThreads), 0, s,
+        hipLaunchKernelGGL((k_split<K, const K *, false>), dim3(g), dim3(th), 0, s,
                            (const K *)data, offs, pl, w, level, mlp);
     }
     return hipGetLastError();
