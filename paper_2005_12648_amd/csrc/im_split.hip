@@ -483,32 +483,34 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
                 if (kl != 2 && kr != 2) {
                     int64_t il = i, ir = la - i;          // kept whole: (|A_X|, |B_X|)
                     ++searches;
-                    if (kl == 1) {
-                        if (LEARNED) {
-                            const int64_t k0 = __shfl(nd.k0, src, 64);
-                            const int64_t i0 = __shfl(nd.i0, src, 64);
-                            const int inst = __shfl(nd.inst, src, 64);
-                            int64_t o0 = offsets[2 * inst], o1 = offsets[2 * inst + 1],
-                                    o2 = offsets[2 * inst + 2];
+                    if (!LEARNED) {
+                        // both children's searches at once: lanes 0-31 split
+                        // L at its own A-length, lanes 32-63 split R (a
+                        // child that is not split searches an empty range)
+                        const bool left = lane < 32;
+                        const bool need = left ? kl == 1 : kr == 1;
+                        const KP A2 = left ? A : A + i;
+                        const KP B2 = left ? B : B + j;
+                        const int64_t a2 = need ? (left ? i : la - i) : 0;
+                        const int64_t b2 = need ? (left ? j : lb - j) : 0;
+                        const int64_t r2 = corank_group<32>(A2, a2, B2, b2, a2, rounds);
+                        const int64_t rl = __shfl(r2, 0, 64), rr = __shfl(r2, 32, 64);
+                        if (kl == 1) il = rl;
+                        if (kr == 1) ir = rr;
+                    } else {
+                        // learned searches, one child after the other
+                        const int64_t k0 = __shfl(nd.k0, src, 64);
+                        const int64_t i0 = __shfl(nd.i0, src, 64);
+                        const int inst = __shfl(nd.inst, src, 64);
+                        const int64_t o0 = offsets[2 * inst], o1 = offsets[2 * inst + 1],
+                                      o2 = offsets[2 * inst + 2];
+                        if (kl == 1)
                             il = corank_group_learned<64>(A, i, B, j, i, mlp, k0 + i, o2 - o0,
                                                           o1 - o0, i0, rounds);
-                        } else {
-                            il = corank_group<64>(A, i, B, j, i, rounds);
-                        }
-                    }
-                    if (kr == 1) {
-                        if (LEARNED) {
-                            const int64_t k0 = __shfl(nd.k0, src, 64);
-                            const int64_t i0 = __shfl(nd.i0, src, 64);
-                            const int inst = __shfl(nd.inst, src, 64);
-                            int64_t o0 = offsets[2 * inst], o1 = offsets[2 * inst + 1],
-                                    o2 = offsets[2 * inst + 2];
+                        if (kr == 1)
                             ir = corank_group_learned<64>(A + i, la - i, B + j, lb - j, la - i, mlp,
                                                           k0 + kk + (la - i), o2 - o0, o1 - o0,
                                                           i0 + i, rounds);
-                        } else {
-                            ir = corank_group<64>(A + i, la - i, B + j, lb - j, la - i, rounds);
-                        }
                     }
                     // child splits (il, jl) of L and (ir, jr) of R; the
                     // whole wave decomposes the permutation
