@@ -402,6 +402,8 @@ def bench_learned(torch, im, oracle, gen, dev, steps):
             "probes_per_diagonal_plain_65537": round(float(probes_p.double().mean()), 2),
             "timing": "median of 3 alternating rounds of %d merges per form, after a warm-up "
                       "merge of each" % k,
+            "rounds_ms_learned": [round(x, 4) for x in rounds_l],
+            "rounds_ms_plain": [round(x, 4) for x in rounds_p],
             "train_s": round(train_s, 3), "mismatches_learned": bad_l, "mismatches_plain": bad_p}
 
 
