@@ -251,12 +251,15 @@ def bench_variant(torch, im, oracle, gen, dev, name, steps):
         return {"workload": "int64 keys in [0,4096) + uint32 payload, 2^26+2^26",
                 "gelem_s": round(n / ms / 1e6, 2), "ms": round(ms, 4), "mismatches": bad,
                 "effective_gb_s": round(2 * 12 * n / ms / 1e6, 1)}
-    if name == "c2_skew":
-        la, lb, hi = 2 ** 23, 2 ** 27 - 2 ** 23, 2 ** 31
+    if name == "c1":
+        la, lb, hi, seed = 2 ** 16, 2 ** 16, 2 ** 31, SEED + 10
+    elif name == "c2_skew":
+        la, lb, hi, seed = 2 ** 23, 2 ** 27 - 2 ** 23, 2 ** 31, SEED + 21
     else:
-        la, lb, hi = 2 ** 27, 2 ** 27, 1024
-    pristine = gen.torch_pair_uniform(la, lb, SEED + (21 if name == "c2_skew" else 22), dev, hi=hi)
-    ms, _, bufs = timed_merges(torch, im, pristine, la, steps, 1)
+        la, lb, hi, seed = 2 ** 27, 2 ** 27, 1024, SEED + 22
+    pristine = gen.torch_pair_uniform(la, lb, seed, dev, hi=hi)
+    # the small merge is launch-bound: time more of them
+    ms, _, bufs = timed_merges(torch, im, pristine, la, 50 if name == "c1" else steps, 1)
     want = oracle.merge(pristine.cpu().numpy(), la)
     bad = mismatches(bufs[0], want)
     n = la + lb
@@ -608,7 +611,7 @@ def main():
     roof = roofline(head["prof"], head["stats"], 4, args.steps, "c2")
     forms = {}
     if args.forms == "all":
-        for name in ("c2_skew", "c2_dup", "c3_kv"):
+        for name in ("c1", "c2_skew", "c2_dup", "c3_kv"):
             log("variant", name)
             forms[name] = bench_variant(torch, im, oracle, gen, dev, name, 3)
             torch.cuda.empty_cache()

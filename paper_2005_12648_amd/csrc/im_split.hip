@@ -378,7 +378,10 @@ __device__ __forceinline__ int child_kind(const Plan &pl, KP A, int64_t la, KP B
 
 // One lane per node classifies it (early exits, leaf); the nodes of a wave
 // that must be split are then searched one after another by the whole wave
-// with the cooperative 64-ary co-rank (a handful of dependent rounds).
+// with the cooperative 64-ary co-rank (a handful of dependent rounds).  A
+// node whose children both split symmetrically has its two levels fused: the
+// children's searches run in the same wave and the node emits the cycles of
+// the composed exchange and its grandchildren (to level + 2).
 template <typename K, typename KP, bool LEARNED>
 __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
                                                          const int64_t *__restrict__ offsets,
