@@ -234,7 +234,7 @@ def bench_headline(torch, im, oracle, gen, dev, args):
 
 
 def bench_variant(torch, im, oracle, gen, dev, name, steps):
-    """Skewed / duplicate-heavy int32 and the key+payload form."""
+    """The small C1 merge, skewed / duplicate-heavy int32 and the key+payload form."""
     if name == "c3_kv":
         la = lb = 2 ** 26
         keys = gen.torch_pair_uniform(la, lb, SEED + 30, dev, hi=4096, dtype=torch.int64)
