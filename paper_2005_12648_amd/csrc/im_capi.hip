@@ -389,6 +389,7 @@ int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *
         hipEvent_t e0 = prof ? prof_begin(s) : nullptr;
         IM_HIP(launch_split(key_dt, keys, offs, pl, w, lv, mlp, s), "launch split");
         prof_end(e0, kStSplit, 1, s);
+        if (lv + 1 == pl.max_levels) break;   // the last level only classifies
         hipEvent_t e1 = prof ? prof_begin(s) : nullptr;
         IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 0, s), "launch rotate A");
         IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");

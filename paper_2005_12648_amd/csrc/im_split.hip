@@ -421,8 +421,12 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
                 // nothing to merge
             } else if (A[la - 1] <= B[0]) {
                 // already in order
-            } else if (A[0] > B[lb - 1]) {
-                emit_rot(pl, w, level, nd.base, la, lb);     // every B before every A
+            } else if (A[0] > B[lb - 1] && level + 1 < pl.max_levels) {
+                // every B before every A: one exchange.  At the last level such
+                // a pair is merged as a leaf instead (every node there is within
+                // the leaf bounds), so that level never exchanges and its
+                // exchange launches are not enqueued.
+                emit_rot(pl, w, level, nd.base, la, lb);
             } else if (la + lb <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) {
                 emit_leaf(pl, w, nd);
             } else if (level + 1 >= pl.max_levels) {
