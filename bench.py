@@ -47,9 +47,14 @@ def src_hash(paths):
     return h.hexdigest()[:16]
 
 
+# Sources whose change makes a committed counter summary stale: the kernel,
+# the shared declarations, and the files that decide its launches and
+# descriptors (plan, launch sequence, split kernel).
 KERNEL_SOURCES = {
-    "leafmerge": ["paper_2005_12648_amd/csrc/im_leaf.hip", "paper_2005_12648_amd/csrc/im_common.h"],
-    "rotate": ["paper_2005_12648_amd/csrc/im_rotate.hip", "paper_2005_12648_amd/csrc/im_common.h"],
+    "leafmerge": ["paper_2005_12648_amd/csrc/im_leaf.hip", "paper_2005_12648_amd/csrc/im_common.h",
+                  "paper_2005_12648_amd/csrc/im_capi.hip"],
+    "rotate": ["paper_2005_12648_amd/csrc/im_rotate.hip", "paper_2005_12648_amd/csrc/im_common.h",
+               "paper_2005_12648_amd/csrc/im_capi.hip", "paper_2005_12648_amd/csrc/im_split.hip"],
     "split": ["paper_2005_12648_amd/csrc/im_split.hip", "paper_2005_12648_amd/csrc/im_search.h"],
     "tilerank": ["paper_2005_12648_amd/csrc/im_split.hip", "paper_2005_12648_amd/csrc/im_search.h"],
     "plan": ["paper_2005_12648_amd/csrc/im_leaf.hip"],
