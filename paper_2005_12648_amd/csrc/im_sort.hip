@@ -10,102 +10,147 @@
 
 namespace imerge {
 
-constexpr int kSortThreads = 512;
-constexpr int kSortIpt = 16;
-constexpr int kSortTile = kSortThreads * kSortIpt;   // 8192 elements
-
-__device__ __forceinline__ int sphys(int x) { return x + (x >> 5); }
+// Tile geometry: 64 KiB of keys per workgroup (two workgroups fill a CU's
+// LDS), 512 threads holding `ipt` keys each.  (Measured on 2^28 int32: this
+// tile with one merge chain of ipt steps per thread and one LDS read per
+// step sorts 8% faster than 8192-key tiles with two reads per step; several
+// shorter chains per thread, each with its own co-rank search, are slower:
+// the rounds are bound by the number of LDS accesses, whose data-dependent
+// addresses conflict in the banks, more than by their latency.)
+template <typename K>
+struct SortGeo {
+    static constexpr int threads = 512;
+    static constexpr int ipt = sizeof(K) == 4 ? 32 : 16;
+    static constexpr int tile = threads * ipt;   // 16384 or 8192 keys
+    // one pad element per 32 words: the blocked accesses (stride ipt keys)
+    // fall in distinct banks
+    static constexpr int shift = sizeof(K) == 4 ? 5 : 4;
+    static constexpr int lds = tile + (tile >> shift) + 8;
+};
 
 template <typename K>
-__global__ __launch_bounds__(kSortThreads) void k_tilesort(K *__restrict__ data, int64_t n) {
-    __shared__ K s[kSortTile + kSortTile / 32 + 1];
+__device__ __forceinline__ int sphys(int x) {
+    return x + (x >> SortGeo<K>::shift);
+}
+
+// Sort of each tile of the array, in place.  Per tile:
+//   1. a coalesced load, IPT keys per thread (which keys a thread starts
+//      with does not matter for a sort);
+//   2. a bitonic network sorts each thread's keys in registers;
+//   3. merge rounds: runs of width w (w = IPT, 2 IPT, ...) held by
+//      consecutive threads are merged pairwise through LDS; a thread finds
+//      the co-rank of its first output by a search in LDS, then merges its
+//      IPT outputs with the next key of each run in registers and the key
+//      type's maximum as the end-of-run sentinel (keys only: an output equal
+//      to the sentinel has the same value whichever side it is taken from);
+//   4. a coalesced store through LDS.
+template <typename K>
+__global__ __launch_bounds__(512, 4) void k_tilesort(K *__restrict__ data, int64_t n) {
+    using SG = SortGeo<K>;
+    constexpr int TH = SG::threads, IPT = SG::ipt, TS = SG::tile;
+    __shared__ K s[SG::lds];
     const int tid = threadIdx.x;
     const K kmax = std::numeric_limits<K>::max();
-    for (int64_t tile = blockIdx.x; tile * kSortTile < n; tile += gridDim.x) {
-        const int64_t t0 = tile * kSortTile;
-        int cnt = (int)(n - t0 < kSortTile ? n - t0 : kSortTile);
-        K r[kSortIpt];
-        // which elements a thread starts with does not matter for a sort:
-        // take a coalesced strided set straight from global memory.
+    for (int64_t tile = blockIdx.x; tile * TS < n; tile += gridDim.x) {
+        const int64_t t0 = tile * TS;
+        const int cnt = (int)(n - t0 < TS ? n - t0 : TS);
+        K r[IPT];
 #pragma unroll
-        for (int u = 0; u < kSortIpt; ++u) {
-            int x = tid + u * kSortThreads;
+        for (int u = 0; u < IPT; ++u) {
+            const int x = tid + u * TH;
             r[u] = x < cnt ? data[t0 + x] : kmax;
         }
-        // odd-even transposition sort of the thread's registers
+        // bitonic sorting network on the thread's registers (ascending)
 #pragma unroll
-        for (int round = 0; round < kSortIpt; ++round) {
+        for (int k = 2; k <= IPT; k <<= 1) {
 #pragma unroll
-            for (int e = round & 1; e + 1 < kSortIpt; e += 2) {
-                K a = r[e], b = r[e + 1];
-                r[e] = a < b ? a : b;
-                r[e + 1] = a < b ? b : a;
+            for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const K x = r[i], y = r[l];
+                        const K mn = x < y ? x : y, mx = x < y ? y : x;
+                        const bool up = (i & k) == 0;
+                        r[i] = up ? mn : mx;
+                        r[l] = up ? mx : mn;
+                    }
+                }
             }
         }
-        // merge rounds: runs of width w held by consecutive threads
-        for (int w = kSortIpt; w < kSortTile; w <<= 1) {
+        for (int w = IPT; w < TS; w <<= 1) {
 #pragma unroll
-            for (int e = 0; e < kSortIpt; ++e) s[sphys(tid * kSortIpt + e)] = r[e];
+            for (int e = 0; e < IPT; ++e) s[sphys<K>(tid * IPT + e)] = r[e];
             __syncthreads();
-            const int dabs = tid * kSortIpt;
-            const int p0 = dabs & ~(2 * w - 1);   // start of the pair of runs
-            const int d = dabs - p0;
-            // co-rank of local diagonal d in runs [p0, p0+w) and [p0+w, p0+2w)
+            const int dabs = tid * IPT;
+            const int p0 = dabs & ~(2 * w - 1);   // the pair of runs [p0, p0+w) | [p0+w, p0+2w)
+            const int pb = p0 + w;
+            const int d = dabs - p0;             // first output diagonal in the pair
             int lo = d > w ? d - w : 0;
             int hi = d < w ? d : w;
             while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (s[sphys(p0 + mid)] <= s[sphys(p0 + w + d - 1 - mid)]) lo = mid + 1;
+                const int mid = (lo + hi) >> 1;
+                if (s[sphys<K>(p0 + mid)] <= s[sphys<K>(pb + d - 1 - mid)]) lo = mid + 1;
                 else hi = mid;
             }
+            // ia, ib: next indices in the two runs; a, b: their keys (the
+            // sentinel once a run is used up).  ia may run past w, by fewer
+            // than IPT steps, which stays inside the pair.
             int ia = lo, ib = d - lo;
+            K a = s[sphys<K>(p0 + ia)];
+            K b = s[sphys<K>(pb + ib)];
+            a = ia < w ? a : kmax;
+            b = ib < w ? b : kmax;
 #pragma unroll
-            for (int e = 0; e < kSortIpt; ++e) {
-                K a = ia < w ? s[sphys(p0 + ia)] : kmax;
-                K b = ib < w ? s[sphys(p0 + w + ib)] : kmax;
-                bool ta = (ib >= w) || (ia < w && a <= b);
+            for (int e = 0; e < IPT; ++e) {
+                const bool ta = a <= b;
                 r[e] = ta ? a : b;
-                if (ta) ++ia; else ++ib;
+                const int na = ia + 1, nb = ib + 1;
+                const K v0 = s[sphys<K>(ta ? p0 + na : pb + nb)];
+                const K v = (ta ? na < w : nb < w) ? v0 : kmax;
+                ia = ta ? na : ia;
+                ib = ta ? ib : nb;
+                a = ta ? v : a;
+                b = ta ? b : v;
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int e = 0; e < kSortIpt; ++e) s[sphys(tid * kSortIpt + e)] = r[e];
+        for (int e = 0; e < IPT; ++e) s[sphys<K>(tid * IPT + e)] = r[e];
         __syncthreads();
+        // (the opaque copy keeps the compiler from hoisting IPT padded
+        // addresses out of the tile loop, which spills)
+        int xb = tid;
+        asm volatile("" : "+v"(xb));
 #pragma unroll
-        for (int u = 0; u < kSortIpt; ++u) {
-            int x = tid + u * kSortThreads;
-            if (x < cnt) data[t0 + x] = s[sphys(x)];
+        for (int u = 0; u < IPT; ++u) {
+            const int x = xb + u * TH;
+            if (x < cnt) data[t0 + x] = s[sphys<K>(x)];
         }
         __syncthreads();
     }
 }
 
-int sort_tile_elems(int) { return kSortTile; }
+int sort_tile_elems(int key_bytes) {
+    return key_bytes == 4 ? SortGeo<int32_t>::tile : SortGeo<int64_t>::tile;
+}
+
+template <typename K>
+static hipError_t tilesort_t(void *data, int64_t n, hipStream_t s) {
+    const int64_t tiles = (n + SortGeo<K>::tile - 1) / SortGeo<K>::tile;
+    const int g = (int)(tiles < 16384 ? (tiles < 1 ? 1 : tiles) : 16384);
+    hipLaunchKernelGGL(k_tilesort<K>, dim3(g), dim3(SortGeo<K>::threads), 0, s, (K *)data, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_tilesort(int key, void *data, int64_t n, hipStream_t s) {
-    int64_t tiles = (n + kSortTile - 1) / kSortTile;
-    int g = (int)(tiles < 8192 ? (tiles < 1 ? 1 : tiles) : 8192);
     switch (key) {
-        case kI32:
-            hipLaunchKernelGGL(k_tilesort<int32_t>, dim3(g), dim3(kSortThreads), 0, s,
-                               (int32_t *)data, n);
-            break;
-        case kU32:
-            hipLaunchKernelGGL(k_tilesort<uint32_t>, dim3(g), dim3(kSortThreads), 0, s,
-                               (uint32_t *)data, n);
-            break;
-        case kI64:
-            hipLaunchKernelGGL(k_tilesort<int64_t>, dim3(g), dim3(kSortThreads), 0, s,
-                               (int64_t *)data, n);
-            break;
-        case kU64:
-            hipLaunchKernelGGL(k_tilesort<uint64_t>, dim3(g), dim3(kSortThreads), 0, s,
-                               (uint64_t *)data, n);
-            break;
-        default: return hipErrorInvalidValue;
+        case kI32: return tilesort_t<int32_t>(data, n, s);
+        case kU32: return tilesort_t<uint32_t>(data, n, s);
+        case kI64: return tilesort_t<int64_t>(data, n, s);
+        case kU64: return tilesort_t<uint64_t>(data, n, s);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 // Instances of one bottom-up pass of width w: [2qw, 2qw+w) | [2qw+w, 2qw+2w),

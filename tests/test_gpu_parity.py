@@ -240,7 +240,9 @@ def test_batched_kv(dev, leaf_tiles):
 
 
 # ------------------------------------------------------------ merge sort
-@pytest.mark.parametrize("n", [1, 2, 8191, 8192, 8193, 100003, 2 ** 20 + 37])
+# sizes around the tile sort's tiles (16384 4-byte or 8192 8-byte keys)
+@pytest.mark.parametrize("n", [1, 2, 8191, 8192, 8193, 16383, 16384, 16385, 100003,
+                               3 * 16384 + 5, 2 ** 20 + 37])
 @pytest.mark.parametrize("dt", [np.int32, np.int64])
 def test_merge_sort(dev, n, dt):
     x = gen.unsorted(n, 77 + n).astype(dt)
@@ -248,6 +250,23 @@ def test_merge_sort(dev, n, dt):
     im.inplace_merge_sort(t)
     torch.cuda.synchronize()
     assert np.array_equal(h(t), oracle.sort_keys(x))
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.uint32, np.int64, np.uint64])
+def test_merge_sort_extreme_keys(dev, dt):
+    # the type's maximum is also the tile sort's end-of-run sentinel: keys
+    # equal to it, to the minimum and heavy duplicates must come out right
+    info = np.iinfo(dt)
+    r = np.random.default_rng(91)
+    for n in (5000, 16384 + 3, 70001):
+        pick = r.integers(0, 6, size=n)
+        x = r.integers(0, 4, size=n).astype(dt)
+        x[pick == 0] = info.max
+        x[pick == 1] = info.min
+        t = torch.from_numpy(x).to(dev)
+        im.inplace_merge_sort(t)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), oracle.sort_keys(x)), (dt.__name__, n)
 
 
 def test_merge_sort_forced_levels(dev, leaf_tiles):
