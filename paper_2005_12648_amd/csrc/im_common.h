@@ -82,6 +82,7 @@ struct Counters {
     unsigned long long levels_used;   // max level index that had nodes, +1
     unsigned long long split_fallbacks;  // FindMedian splits replaced by co-rank splits
     unsigned long long fused;            // nodes whose two levels ran as one exchange
+    unsigned long long leaf_next;        // leaf merge: slots handed out beyond the static ones
     unsigned int error;               // nonzero: a device-side check failed
     unsigned int pad;
 };

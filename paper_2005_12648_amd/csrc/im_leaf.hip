@@ -316,100 +316,139 @@ struct LeafOps {
     }
 };
 
-// Pipeline state of one workgroup: tile t (merged, in registers `cur`),
-// tile t+G (staged in LDS), and their geometry.
+// Slots after each workgroup's static ones come from a counter, in
+// increasing order, so that a workgroup that runs slower takes fewer tiles
+// instead of falling behind the others (with s -> s mod G the slowest
+// workgroup sets the pace, and the others wait for its tiles' flags).  A
+// workgroup takes a slot only after its wait of the step before the slot is
+// staged, so a waiting workgroup has staged every slot it holds; thread 0
+// takes it and hands it over through LDS after the next merge, by which
+// time the counter's answer has long returned.
+__device__ __forceinline__ unsigned long long take_slot(const Work &w) {
+    return atomicAdd(&w.ctr->leaf_next, 1ull);
+}
+
+// The slot taken last step (thread 0's `pend`, offset by the static slots),
+// as a wave-uniform value in every thread.
+__device__ __forceinline__ int64_t hand_over(int64_t *s_slot, unsigned long long pend,
+                                             int64_t first, int64_t ntiles, bool taken) {
+    if (threadIdx.x == 0) s_slot[0] = taken ? first + (int64_t)pend : ntiles;
+    __syncthreads();
+    return uniform64(s_slot[0]);
+}
+
+// Pipeline state of one workgroup: tile g (merged, in registers `cur`),
+// tile g1 (staged in LDS), and whether g1 exists.
 struct LeafPipe {
-    int64_t t, ntiles;
-    bool has1;            // tile t+G exists (and is staged)
+    int64_t ntiles, first;  // tiles; first slot handed out by the counter (2G)
+    bool has1;
     TileGeo g, g1;
 };
 
-// One step: merge t+G from LDS into `nxt`, stage t+2G into LDS, wait for
-// the readers of t's window, store t from `cur`, advance.  Returns false
-// after the workgroup's last tile.
+// One step: merge g1 from LDS into `nxt`, stage the slot taken last step
+// into LDS, wait for the readers of g's window, take the next slot, store g
+// from `cur`, advance.  Returns false after the workgroup's last tile.
 template <typename K, typename V, int THREADS, int IPT>
 __device__ __forceinline__ bool leaf_step(K *keys, V *vals, K *sk, V *sv, const Plan &pl,
-                                          const Work &w, LeafPipe &p,
+                                          const Work &w, LeafPipe &p, int64_t *s_slot,
+                                          unsigned long long &pend,
                                           K (&cur)[IPT], V (&vcur)[LeafOps<K, V, THREADS, IPT>::VN],
                                           K (&nxt)[IPT], V (&vnxt)[LeafOps<K, V, THREADS, IPT>::VN]) {
     using Ops = LeafOps<K, V, THREADS, IPT>;
-    const int64_t G = gridDim.x;
     if (p.has1) Ops::template merge<true>(p.g1, sk, sv, nxt, vnxt);
-    const int64_t t2 = p.t + 2 * G;
+    const int64_t t2 = hand_over(s_slot, pend, p.first, p.ntiles, p.has1);
     const bool has2 = p.has1 && t2 < p.ntiles;
     TileGeo g2 = p.g1;
     if (has2) {
         g2 = tile_geo(w, t2, Ops::T);
         Ops::stage(keys, vals, g2, sk, sv, pl, w);
     }
-    if (Ops::wait_readers(p.g, pl, w)) Ops::store(keys, vals, p.g, cur, vcur);
+    const bool ready = Ops::wait_readers(p.g, pl, w);
+    if (threadIdx.x == 0 && has2) pend = take_slot(w);
+    if (ready) Ops::store(keys, vals, p.g, cur, vcur);
     if (!p.has1) return false;
-    p.t += G;
     p.g = p.g1;
     p.has1 = has2;
     p.g1 = g2;
     return true;
 }
 
-// Pipeline per workgroup (slots t, t+G, t+2G, ...).
-//   DEPTH 2: merge t from LDS into registers, stage t+G into LDS and flag it,
-//            wait for the readers of t's window, store t.  Two tiles are read
-//            at or beyond the oldest unstored slot: readers may be up to
-//            2G-1 slots ahead.
-//   DEPTH 3: tile t waits and is stored only after t+G has been merged into
-//            a second register set and t+2G has been staged into LDS and
-//            flagged: readers may be up to 3G-1 slots ahead (larger leaves,
-//            fewer division levels), at the price of a second register set.
+// Pipeline per workgroup (its static slots b and b+G, then slots from the
+// counter; the deadlock argument at the top of this file holds because the
+// slots handed out are contiguous and every waiting workgroup holds `depth`
+// staged slots, so the slots staged when all wait reach depth*G past the
+// oldest unstored one).
+//   DEPTH 2: merge t from LDS into registers, stage the next slot into LDS
+//            and flag it, wait for the readers of t's window, store t.
+//            Readers may be up to 2G-1 slots ahead.
+//   DEPTH 3: tile t waits and is stored only after the next slot has been
+//            merged into a second register set and the one after staged
+//            into LDS and flagged: readers may be up to 3G-1 slots ahead
+//            (larger leaves, fewer division levels), at the price of a
+//            second register set.
 template <typename K, typename V, int THREADS, int IPT, int DEPTH>
 __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
                                                           Plan pl, Work w) {
     using Ops = LeafOps<K, V, THREADS, IPT>;
     static_assert(DEPTH == 2 || DEPTH == 3, "pipeline depth");
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t s_slot[1];
     K *sk = reinterpret_cast<K *>(smem);
     V *sv = reinterpret_cast<V *>(smem + (size_t)Ops::PE * sizeof(K));
 
     LeafPipe p;
     p.ntiles = (int64_t)w.ctr->tiles;
     if (p.ntiles > pl.cap_tiles) p.ntiles = pl.cap_tiles;
-    p.t = blockIdx.x;
-    if (p.t >= p.ntiles) return;
+    const int64_t t0 = blockIdx.x;
+    if (t0 >= p.ntiles) return;
     const int64_t G = gridDim.x;
+    unsigned long long pend = 0;   // thread 0: the counter value taken last
 
     K ra[IPT];
     V va[Ops::VN];
-    p.g = tile_geo(w, p.t, Ops::T);
+    p.g = tile_geo(w, t0, Ops::T);
     Ops::stage(keys, vals, p.g, sk, sv, pl, w);
     if constexpr (DEPTH == 2) {
+        p.first = G;
+        bool more = t0 + G < p.ntiles;
+        if (threadIdx.x == 0 && more) pend = take_slot(w);
         for (;;) {
             Ops::template merge<false>(p.g, sk, sv, ra, va);
-            const int64_t tn = p.t + G;
+            const int64_t tn = hand_over(s_slot, pend, p.first, p.ntiles, more);
             const bool has_next = tn < p.ntiles;
             TileGeo gn = p.g;
             if (has_next) {
                 gn = tile_geo(w, tn, Ops::T);
                 Ops::stage(keys, vals, gn, sk, sv, pl, w);
             }
-            if (Ops::wait_readers(p.g, pl, w)) Ops::store(keys, vals, p.g, ra, va);
+            const bool ready = Ops::wait_readers(p.g, pl, w);
+            if (threadIdx.x == 0 && has_next) pend = take_slot(w);
+            if (ready) Ops::store(keys, vals, p.g, ra, va);
             if (!has_next) break;
-            p.t = tn;
+            more = true;
             p.g = gn;
         }
     } else {
         K rb[IPT];
         V vb[Ops::VN];
-        // prologue: t into registers, t+G into LDS
+        // prologue: b into registers, b+G into LDS, the next slot taken
+        p.first = 2 * G;
         Ops::template merge<true>(p.g, sk, sv, ra, va);
-        p.has1 = p.t + G < p.ntiles;
+        p.has1 = t0 + G < p.ntiles;
         p.g1 = p.g;
         if (p.has1) {
-            p.g1 = tile_geo(w, p.t + G, Ops::T);
+            p.g1 = tile_geo(w, t0 + G, Ops::T);
             Ops::stage(keys, vals, p.g1, sk, sv, pl, w);
+            if (threadIdx.x == 0) pend = take_slot(w);
         }
         // the two register sets alternate roles
         for (;;) {
-            if (!leaf_step<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, ra, va, rb, vb)) break;
-            if (!leaf_step<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, rb, vb, ra, va)) break;
+            if (!leaf_step<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, s_slot, pend, ra, va,
+                                               rb, vb))
+                break;
+            if (!leaf_step<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, s_slot, pend, rb, vb,
+                                               ra, va))
+                break;
         }
     }
 }
