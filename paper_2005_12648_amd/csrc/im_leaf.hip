@@ -17,20 +17,23 @@
 //      B elements only move left, so the readers form one contiguous range
 //      of tiles around the tile itself);
 //   5. coalesced store of the window.
-// The grid is persistent and co-resident (cooperative launch); processing
-// slot s is handled by workgroup s mod G in increasing s.  Within a leaf the
-// slots visit the tiles in increasing order when every A element moves right
-// by at most the leaf span (the leaf's B-part is within the span, or the
-// whole leaf is within the leaf capacity), else in decreasing order (then
-// its A-part is within the span and every B element moves left by at most
-// the span).  The planner keeps every reader less than 3G slots after the
-// tile it reads.  Deadlock
-// freedom: let s be the smallest slot not yet stored.  Every workgroup has
-// stored all its slots below s, so it sits at its first slot c >= s
-// (c < s+G); before its first wait it has read c, c+G and c+2G (one tile in
-// registers, one merged into a second register set, one staged in LDS).  The
-// slots [s, s+3G) are therefore all read without any wait, the readers of
-// s's window are among them, and s is stored.  The wait is bounded: on
+// The grid is persistent and co-resident (cooperative launch).  Workgroup b
+// takes slots b and b+G (b alone at depth 2) and then further slots from a
+// device counter, in increasing order, each after the wait of the step
+// before the slot is staged.  Within a leaf the slots visit the tiles in
+// increasing order when every A element moves right by at most the leaf
+// span (the leaf's B-part is within the span, or the whole leaf is within
+// the leaf capacity), else in decreasing order (then its A-part is within
+// the span and every B element moves left by at most the span).  The
+// planner keeps every reader less than depth*G slots after the tile it
+// reads.  Deadlock freedom (depth 3): suppose every workgroup that still has
+// tiles waits, and let s be the smallest slot not yet stored.  A waiting
+// workgroup has staged every slot it holds: the one it waits to store, one
+// merged into a second register set and one staged in LDS, all at or after
+// s.  Either every slot has been handed out (and so staged), or each
+// workgroup holds three, and the contiguous handed-out range reaches at
+// least s+3G.  Either way the readers of s's window, less than 3G slots
+// after s, have read their inputs, so s is stored.  The wait is bounded: on
 // expiry the workgroup raises an error bit and skips its store.
 #include <limits>
 #include <type_traits>
@@ -466,7 +469,8 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
 //      output order: chunk c of the tile is chunk c of its output window;
 //   4. "inputs read" is published once every load has returned;
 //   5. after the readers of the window have published, a coalesced store.
-// Grid, slot order and reader ranges are those of k_leafmerge.  A workgroup
+// Grid, slot order and reader ranges are those of k_leafmerge at depth 2
+// (slot b, then slots from the counter).  A workgroup
 // holds two tiles in registers, the one waiting to be stored and the next,
 // which it reads before it waits: the depth-2 argument above applies, so a
 // leaf may have 2G tiles.
@@ -575,18 +579,22 @@ struct RowOps {
 template <typename K, int CH>
 __device__ __forceinline__ bool row_step(unsigned char *data, const RowGeo &rg, const Plan &pl,
                                          const Work &w, K *sk, int64_t *so, int64_t ntiles,
-                                         int64_t &t, TileGeo &g,
+                                         int64_t &t, TileGeo &g, int64_t *s_slot,
+                                         unsigned long long &pend, bool &more,
                                          typename RowOps<K, CH>::C (&cur)[RowOps<K, CH>::CPT],
                                          typename RowOps<K, CH>::C (&nxt)[RowOps<K, CH>::CPT]) {
-    const int64_t tn = t + gridDim.x;
+    const int64_t tn = hand_over(s_slot, pend, gridDim.x, ntiles, more);
     const bool has = tn < ntiles;
     TileGeo gn = g;
     if (has) {
         gn = tile_geo(w, tn, rg.R);
         RowOps<K, CH>::read(data, rg, gn, sk, so, nxt, pl, w);
     }
-    if (wait_window<kRowThreads>(g, pl, w)) RowOps<K, CH>::store(data, rg, g, cur);
+    const bool ready = wait_window<kRowThreads>(g, pl, w);
+    if (threadIdx.x == 0 && has) pend = take_slot(w);
+    if (ready) RowOps<K, CH>::store(data, rg, g, cur);
     if (!has) return false;
+    more = true;
     t = tn;
     g = gn;
     return true;
@@ -600,14 +608,18 @@ __global__ __launch_bounds__(kRowThreads, 4) void k_leafrows(unsigned char *__re
     __shared__ int64_t so[kRowMaxRows];
     int64_t ntiles = (int64_t)w.ctr->tiles;
     if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
+    __shared__ int64_t s_slot[1];
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
     typename Ops::C ra[Ops::CPT], rb[Ops::CPT];
     TileGeo g = tile_geo(w, t, rg.R);
     Ops::read(data, rg, g, sk, so, ra, pl, w);
+    bool more = t + gridDim.x < ntiles;
+    unsigned long long pend = 0;
+    if (threadIdx.x == 0 && more) pend = take_slot(w);
     for (;;) {
-        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, ra, rb)) break;
-        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, rb, ra)) break;
+        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, s_slot, pend, more, ra, rb)) break;
+        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, s_slot, pend, more, rb, ra)) break;
     }
 }
 
