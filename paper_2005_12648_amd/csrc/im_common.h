@@ -83,6 +83,7 @@ struct Counters {
     unsigned long long split_fallbacks;  // FindMedian splits replaced by co-rank splits
     unsigned long long fused;            // nodes whose two levels ran as one exchange
     unsigned long long leaf_next;        // leaf merge: slots handed out beyond the static ones
+    unsigned long long rot_next[kMaxLevels][2];  // exchanges: items handed out per level and phase
     unsigned int error;               // nonzero: a device-side check failed
     unsigned int pad;
 };

@@ -168,14 +168,23 @@ struct ValRegs<NoVal, MAXC, PER> {};
 // pipelined 5.1-5.3 TB/s; one workgroup per item reaches 5.2 TB/s, but an
 // empty launch of such a grid costs about 18 us against 6 us, and the
 // phase-1 launch is empty whenever a level has only block swaps.)
+// Items go to workgroups in grid-stride order for 512-thread workgroups
+// (elements of 4 bytes).  1024-thread workgroups (wider elements) take their
+// first item by index and the rest from a per-level, per-phase counter:
+// thread 0 takes the next index one item ahead and hands it over through
+// LDS, so the counter's latency hides behind an item.  (Measured: the
+// counter makes the 2^26+2^26 int64+uint32 merge 4% faster at a grid of
+// 1024 and the 2^27+2^27 int32 merge 7-23% slower at grids of 2048-6144.)
 template <typename EK, typename EV,
           typename G = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>>
 __global__ __launch_bounds__(G::threads) void k_rotate(EK *__restrict__ keys, EV *__restrict__ vals,
                                                        const Rot *__restrict__ rot,
-                                                       const Counters *__restrict__ ctr,
+                                                       Counters *__restrict__ ctr,
                                                        int64_t cap_rot, int level, int phase) {
     constexpr bool HAS_V = !std::is_same<EV, NoVal>::value;
     constexpr int TH = G::threads, MAXC = G::maxc, PER = G::per;
+    constexpr bool DYN = TH >= 1024;   // items from the counter after the first
+    __shared__ int64_t s_item[2];
     if (phase == 1 && ctr->level_rev[level] == 0) return;   // only swaps and cycles
     const unsigned long long packed = ctr->level_rot[level];
     int64_t nrot = (int64_t)(packed >> kRotCountShift);
@@ -190,7 +199,10 @@ __global__ __launch_bounds__(G::threads) void k_rotate(EK *__restrict__ keys, EV
     CycItem cur;
     CycRegs<EK, MAXC, PER> kr;
     ValRegs<EV, MAXC, PER> vr;
-    for (int64_t wi = blockIdx.x;; wi += gridDim.x) {
+    unsigned long long pend = 0;   // thread 0: counter value for the item after next
+    if (DYN && threadIdx.x == 0) pend = atomicAdd(&ctr->rot_next[level][phase], 1ull);
+    int par = 0;
+    for (int64_t wi = blockIdx.x;;) {
         CycItem nx;
         nx.lim = 0;
         if (wi < nitems) {
@@ -221,6 +233,19 @@ __global__ __launch_bounds__(G::threads) void k_rotate(EK *__restrict__ keys, EV
             have = true;
         }
         if (wi >= nitems) break;
+        if constexpr (DYN) {
+            // an index taken after one at or past nitems is past it too, so
+            // an unused last take loses no item
+            if (threadIdx.x == 0) {
+                s_item[par] = (int64_t)gridDim.x + (int64_t)pend;
+                pend = atomicAdd(&ctr->rot_next[level][phase], 1ull);
+            }
+            __syncthreads();
+            wi = s_item[par];
+            par ^= 1;
+        } else {
+            wi += gridDim.x;
+        }
     }
     if (have) {
         item_store<EK, TH, MAXC, PER>(keys, cur, kr);
@@ -420,14 +445,15 @@ hipError_t launch_rotate_cs_single(void *data, int64_t lx, int64_t ly, int esize
 template <typename EK, typename EV>
 static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, int level,
                         int phase, hipStream_t s) {
-    // Persistent grid several times larger than the chip holds at once:
-    // workgroups that finish early are replaced, which balances the items.
-    // (Measured on the exchange stage of 2^28-element merges, grids of
-    // 768 ... 16384: exactly the resident workgroups is 6-13% slower than
-    // 2048; 6144 is best for 512-thread workgroups (int32: -6% against
-    // 2048), 4096 for 1024-thread ones (int64, key+payload: -3 to -5%).)
+    // 512-thread workgroups (grid-stride items): a grid several times larger
+    // than the chip holds at once, so that workgroups that finish early are
+    // replaced, which balances the items.  (Measured on the exchange stage
+    // of 2^28-element merges, grids of 768 ... 16384: exactly the resident
+    // workgroups is 6-13% slower than 2048; 6144 is best, -6% against 2048.)
+    // 1024-thread workgroups take items from a counter, which balances them
+    // without replacement: 1024 (best of 1024, 2048 and 4096).
     constexpr int TH = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>::threads;
-    const int g = TH == 512 ? 6144 : 4096;
+    const int g = TH == 512 ? 6144 : 1024;
     hipLaunchKernelGGL((k_rotate<EK, EV>), dim3(g), dim3(TH), 0, s, (EK *)keys, (EV *)vals,
                        w.rot, w.ctr, pl.cap_rot, level, phase);
     return hipGetLastError();

@@ -31,11 +31,11 @@ __global__ void k_init(Counters *ctr, Node *nodes0, const int64_t *__restrict__ 
                        int64_t n_inst, int64_t la, int64_t lb, int64_t *off1) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    constexpr int kWords = (int)(sizeof(Counters) / sizeof(unsigned long long));
-    if (gid < kWords) {
+    constexpr int64_t kWords = (int64_t)(sizeof(Counters) / sizeof(unsigned long long));
+    static_assert(sizeof(Counters) % sizeof(unsigned long long) == 0, "whole words");
+    for (int64_t q = gid; q < kWords; q += stride) {
         // level_nodes[0] is the first word: it starts at the number of roots.
-        reinterpret_cast<unsigned long long *>(ctr)[gid] =
-            gid == 0 ? (unsigned long long)n_inst : 0ull;
+        reinterpret_cast<unsigned long long *>(ctr)[q] = q == 0 ? (unsigned long long)n_inst : 0ull;
     }
     if (offsets == nullptr) {
         // single instance: A = [0, la), B = [la, la+lb)
