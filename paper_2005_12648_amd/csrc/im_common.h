@@ -151,7 +151,7 @@ struct Work {
     int64_t *tile_start;     // per leaf: first tile index (exclusive scan)
     int64_t *tile_rank;      // per tile: co-rank at the tile's first diagonal
     int32_t *tile_leaf;      // per tile: its leaf
-    int32_t *tile_dep;       // per tile: [lo, hi] leaf-local tiles reading its window
+    int32_t *tile_dep;       // per tile: leaf-local tiles reading its window, A [lo, hi], B [lo, hi]
     unsigned int *tile_flag; // per tile: == epoch once its inputs are in LDS
     int64_t *offsets1;       // [3] offsets of a single-instance call
     void *cs_stash_k;        // circular shifting: first value of each cycle segment

@@ -13,9 +13,11 @@
 //      of the same leaf.  Every tile publishes "inputs read" in its own flag
 //      as soon as its slices are in LDS; before storing, a tile waits for
 //      the flags of exactly the tiles that read its window (k_tiledeps
-//      computes that range from the co-ranks: A elements only move right,
-//      B elements only move left, so the readers form one contiguous range
-//      of tiles around the tile itself);
+//      computes them from the co-ranks: the tiles whose A-slices meet the
+//      window's A elements and those whose B-slices meet its B elements,
+//      two contiguous ranges of a few tiles each; A elements only move
+//      right and B elements only move left, so the first range starts at or
+//      after the tile and the second ends at or before it);
 //   5. coalesced store of the window.
 // The grid is persistent and co-resident (cooperative launch).  Workgroup b
 // takes slots b and b+G (b alone at depth 2) and then further slots from a
@@ -62,7 +64,8 @@ __device__ __forceinline__ K key_max() {
 struct TileGeo {
     int64_t out0, a0, b0, tbase;
     int n, na;
-    int32_t ntiles, local, wlo, whi;
+    int32_t ntiles, local;
+    int32_t alo, ahi, blo, bhi;   // readers: A-slices [alo, ahi], B-slices [blo, bhi]
 };
 
 // The slot index is the same in every lane: the geometry is read once per
@@ -111,8 +114,10 @@ __device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t s, int T) {
     g.ntiles = ntiles;
     g.tbase = tstart;
     g.local = (int32_t)local;
-    g.wlo = uniform32(w.tile_dep[2 * t]);
-    g.whi = uniform32(w.tile_dep[2 * t + 1]);
+    g.alo = uniform32(w.tile_dep[4 * t]);
+    g.ahi = uniform32(w.tile_dep[4 * t + 1]);
+    g.blo = uniform32(w.tile_dep[4 * t + 2]);
+    g.bhi = uniform32(w.tile_dep[4 * t + 3]);
     return g;
 }
 
@@ -177,8 +182,11 @@ __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" :
 template <int THREADS>
 __device__ __forceinline__ bool wait_window(const TileGeo &g, const Plan &pl, const Work &w) {
     if (g.ntiles <= 1) return true;
+    const int na = g.ahi >= g.alo ? g.ahi - g.alo + 1 : 0;
+    const int nb = g.bhi >= g.blo ? g.bhi - g.blo + 1 : 0;
     int bad = 0;
-    for (int q = g.wlo + (int)threadIdx.x; q <= g.whi && !bad; q += THREADS) {
+    for (int x = (int)threadIdx.x; x < na + nb && !bad; x += THREADS) {
+        const int q = x < na ? g.alo + x : g.blo + (x - na);
         if (q == g.local) continue;
         const unsigned *f = &w.tile_flag[g.tbase + q];
         unsigned spins = 0;
@@ -717,8 +725,10 @@ __global__ __launch_bounds__(THREADS, 4) void k_merge_oop(const K *__restrict__ 
     g.tbase = 0;
     g.ntiles = 1;
     g.local = 0;
-    g.wlo = 0;
-    g.whi = 0;
+    g.alo = 0;
+    g.ahi = -1;
+    g.blo = 0;
+    g.bhi = -1;
     stage_tile_dma<K, THREADS, IPT>(in, g, sk);
     wait_dma();
     if (threadIdx.x == 0) sk[g.n] = key_max<K>();   // B sentinel
@@ -833,13 +843,16 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Plan pl, Work w) {
 }
 
 // Readers of each tile's window.  Tile i of a leaf (parts la, lb, size S)
-// writes [iT, min((i+1)T, S)).  The A elements there, [iT, min((i+1)T, la)),
-// are read by the tiles j whose A-slice [ia(j), ia(j+1)) meets that range;
-// A elements only move right, so these are tiles >= i and the last one is
-// the last j with ia(j) < min((i+1)T, la).  The B elements there, B indices
-// [max(iT, la) - la, min((i+1)T, S) - la), only move left: their readers
-// are tiles <= i, the first being the first j with jb(j+1) > max(iT,la)-la,
-// where jb(j) = min(jT, S) - ia(j).  dep = [first B reader, last A reader].
+// writes [iT, min((i+1)T, S)).  The A elements there, [pa0, pa1) =
+// [iT, min((i+1)T, la)), are read by the tiles j whose A-slice
+// [ia(j), ia(j+1)) meets that range: from the first j with ia(j+1) > pa0 to
+// the last j with ia(j) < pa1.  The B elements there, B indices
+// [pb0, pb1) = [max(iT, la) - la, min((i+1)T, S) - la), are read by the tiles
+// whose B-slice [jb(j), jb(j+1)) meets it, jb(j) = min(jT, S) - ia(j): from
+// the first j with jb(j+1) > pb0 to the last j with jb(j) < pb1.  An empty
+// range is stored as [0, -1].  (Every tile between the window and its last
+// reader used to be polled as well: hundreds of device-scope flag loads per
+// tile on large leaves, against a handful.)
 __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
     int64_t ntiles = (int64_t)w.ctr->tiles;
     if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
@@ -852,7 +865,7 @@ __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
         const int64_t nt = lf.ntiles;
         const int64_t i = t - ts;
         const int64_t S = lf.la + lf.lb;
-        int64_t wlo = i, whi = i;
+        int64_t alo = 0, ahi = -1, blo = 0, bhi = -1;
         if (nt > 1) {
             auto ia = [&](int64_t j) -> int64_t { return j < nt ? w.tile_rank[ts + j] : lf.la; };
             auto jb = [&](int64_t j) -> int64_t {
@@ -862,26 +875,41 @@ __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
             const int64_t pa0 = i * T;
             const int64_t pa1 = (i + 1) * T < lf.la ? (i + 1) * T : lf.la;
             if (pa0 < lf.la) {                       // window holds A elements
-                int64_t lo = 0, hi = nt - 1;         // ia(0) = 0 < pa1
+                int64_t lo = 0, hi = nt - 1;         // ia(nt) = la > pa0
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    if (ia(mid + 1) > pa0) hi = mid; else lo = mid + 1;
+                }
+                alo = lo;
+                lo = 0; hi = nt - 1;                 // ia(0) = 0 < pa1
                 while (lo < hi) {
                     int64_t mid = (lo + hi + 1) >> 1;
                     if (ia(mid) < pa1) lo = mid; else hi = mid - 1;
                 }
-                if (lo > whi) whi = lo;
+                ahi = lo;
             }
             const int64_t e = (i + 1) * T < S ? (i + 1) * T : S;
             if (e > lf.la) {                         // window holds B elements
                 const int64_t pb0 = (pa0 > lf.la ? pa0 : lf.la) - lf.la;
+                const int64_t pb1 = e - lf.la;
                 int64_t lo = 0, hi = nt - 1;         // jb(nt) = lb > pb0
                 while (lo < hi) {
                     int64_t mid = (lo + hi) >> 1;
                     if (jb(mid + 1) > pb0) hi = mid; else lo = mid + 1;
                 }
-                if (lo < wlo) wlo = lo;
+                blo = lo;
+                lo = 0; hi = nt - 1;                 // jb(0) = 0 < pb1
+                while (lo < hi) {
+                    int64_t mid = (lo + hi + 1) >> 1;
+                    if (jb(mid) < pb1) lo = mid; else hi = mid - 1;
+                }
+                bhi = lo;
             }
         }
-        w.tile_dep[2 * t] = (int32_t)wlo;
-        w.tile_dep[2 * t + 1] = (int32_t)whi;
+        w.tile_dep[4 * t] = (int32_t)alo;
+        w.tile_dep[4 * t + 1] = (int32_t)ahi;
+        w.tile_dep[4 * t + 2] = (int32_t)blo;
+        w.tile_dep[4 * t + 3] = (int32_t)bhi;
     }
 }
 
