@@ -121,3 +121,26 @@ def test_balanced_leaf_beyond_g_tiles(dev, half):
         assert np.array_equal(got, want)
     finally:
         im.set_config(-1)
+
+
+@pytest.mark.parametrize("grid", [1, 3, 7])
+@pytest.mark.parametrize("kd,vd", [(np.int64, np.uint32), (np.int32, np.uint64)])
+def test_small_grid_key_payload(dev, small_grid, monkeypatch, grid, kd, vd):
+    # key+payload leaves with readers far ahead at a tiny grid, and leaf
+    # capacities of a few tiles so that the exchanges of 1024-thread
+    # workgroups run several levels
+    small_grid(grid)
+    for tiles in (None, 3):
+        if tiles is None:
+            monkeypatch.delenv("IM_LEAF_TILES", raising=False)
+        else:
+            monkeypatch.setenv("IM_LEAF_TILES", str(tiles))
+        for la, lb in [(60_001, 59_999), (5, 90_000), (90_000, 5)]:
+            keys = gen.pair_uniform(la, lb, 11 * la + lb + grid, hi=512, dtype=kd)
+            vals = np.arange(la + lb, dtype=vd)
+            say("kv grid", grid, "tiles", tiles, kd.__name__, vd.__name__, la, lb)
+            tk, tv = d(keys, dev), d(vals, dev)
+            im.inplace_merge_kv(tk, tv, la)
+            wk, wv = oracle.merge_kv(keys, vals, la)
+            assert np.array_equal(tk.cpu().numpy(), wk)
+            assert np.array_equal(tv.cpu().numpy(), wv)
