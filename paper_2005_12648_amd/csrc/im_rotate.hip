@@ -451,9 +451,13 @@ static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, i
     // of 2^28-element merges, grids of 768 ... 16384: exactly the resident
     // workgroups is 6-13% slower than 2048; 6144 is best, -6% against 2048.)
     // 1024-thread workgroups take items from a counter, which balances them
-    // without replacement: 1024 (best of 1024, 2048 and 4096).
+    // without replacement: 1024 (best of 1024, 2048 and 4096).  Phase 1 (the
+    // last reversal of three-reversal exchanges) is empty on balanced levels,
+    // and an empty launch costs about its dispatch: 1024 workgroups there
+    // (measured: int32 2^27+2^27 merge -0.7%, 64-byte rows -1.2%, the
+    // 4096-instance batch, which has phase-1 work, unchanged).
     constexpr int TH = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>::threads;
-    const int g = TH == 512 ? 6144 : 1024;
+    const int g = phase == 1 ? 1024 : (TH == 512 ? 6144 : 1024);
     hipLaunchKernelGGL((k_rotate<EK, EV>), dim3(g), dim3(TH), 0, s, (EK *)keys, (EV *)vals,
                        w.rot, w.ctr, pl.cap_rot, level, phase);
     return hipGetLastError();
