@@ -52,12 +52,14 @@ def src_hash(paths):
 # descriptors (plan, launch sequence, split kernel).
 KERNEL_SOURCES = {
     "leafmerge": ["paper_2005_12648_amd/csrc/im_leaf.hip", "paper_2005_12648_amd/csrc/im_common.h",
-                  "paper_2005_12648_amd/csrc/im_capi.hip"],
+                  "paper_2005_12648_amd/csrc/im_capi.hip", "paper_2005_12648_amd/csrc/im_split.hip"],
     "rotate": ["paper_2005_12648_amd/csrc/im_rotate.hip", "paper_2005_12648_amd/csrc/im_common.h",
                "paper_2005_12648_amd/csrc/im_capi.hip", "paper_2005_12648_amd/csrc/im_split.hip"],
     "split": ["paper_2005_12648_amd/csrc/im_split.hip", "paper_2005_12648_amd/csrc/im_search.h"],
     "tilerank": ["paper_2005_12648_amd/csrc/im_split.hip", "paper_2005_12648_amd/csrc/im_search.h"],
-    "plan": ["paper_2005_12648_amd/csrc/im_leaf.hip"],
+    # (leaf planning has no kernel of its own: leaves get their tiles where
+    # the split kernel emits them)
+    "plan": ["paper_2005_12648_amd/csrc/im_split.hip"],
 }
 
 

@@ -280,8 +280,9 @@ int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream);
 /* Stage timing for the calling thread.  While enabled, every merge records
  * HIP events on its stream around its launch groups; _read synchronises
  * `stream`, adds the elapsed milliseconds per stage into ms[0..nstages)
- * (0: split searches, 1: partition exchanges, 2: leaf planning, 3: tile
- * co-ranks, 4: leaf merge), the number of kernel launches into launches[]
+ * (0: split searches, 1: partition exchanges, 2: leaf planning (no launch
+ * of its own: leaves are laid out as they are emitted, so it reads 0),
+ * 3: tile co-ranks, 4: leaf merge), the number of kernel launches into launches[]
  * (may be NULL), and forgets the recorded events. */
 int inplace_merge_profile(int enable);
 int inplace_merge_profile_read(double *ms, int64_t *launches, int nstages, hipStream_t stream);

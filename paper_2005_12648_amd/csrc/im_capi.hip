@@ -26,6 +26,8 @@ thread_local Counters *g_last_ctr = nullptr;
 // Stage timing (inplace_merge_profile): events recorded on the caller's
 // stream around each group of launches, read back by
 // inplace_merge_profile_read.
+// (stage 2, leaf planning, has had no launch since leaves get their tiles as
+// they are emitted; it stays in the numbering of the public API and reads 0)
 enum { kStSplit = 0, kStRotate = 1, kStPlan = 2, kStTileRank = 3, kStLeafMerge = 4, kStCount = 5 };
 struct ProfRec {
     int stage;
@@ -144,6 +146,17 @@ DevState *dev_state(int *dev_out) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Split of the packed leaf/tile counter: enough low bits for every tile of
+// the leaves within cap_leaves, the high bits for the leaf index (one bit to
+// spare).  0 when the two do not fit in 64 bits (about 2^31 instances at
+// once); such a plan is refused.
+int leaf_shift(const Plan &pl) {
+    int tb = 1, lb = 1;
+    while (tb < 62 && (int64_t(1) << tb) <= pl.cap_tiles) ++tb;
+    while (lb < 62 && (int64_t(1) << lb) <= pl.cap_leaves) ++lb;
+    return tb + lb + 1 <= 64 ? tb : 0;
+}
+
 // Sizes and derived limits of one pipeline run.
 bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int64_t max_inst,
                int cfg, Plan *pl) {
@@ -200,7 +213,7 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     // only for elements of at most 12 bytes.  IM_FUSE=0 turns it off.
     const char *fz = std::getenv("IM_FUSE");
     pl->fuse = (ek + ev <= 12 && !(fz && fz[0] == '0')) ? 1 : 0;
-    pl->pad2 = 0;
+    pl->leaf_shift = 0;
     pl->row_stride = 0;
     pl->rot_scale = 1;
     // A node is split only when it exceeds the leaf capacity, so a level has
@@ -213,6 +226,7 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->cap_rot = pl->cap_nodes + 20 * per + 16;
     pl->cap_leaves = n_inst + 6 * (int64_t)lv * per + 16;
     pl->cap_tiles = total / pl->tile + pl->cap_leaves + 16;
+    pl->leaf_shift = leaf_shift(*pl);
     return true;
 }
 
@@ -258,7 +272,7 @@ bool make_plan_rows(DevState *ds, int key_dt, int64_t row_bytes, int ch, int64_t
     pl->cap_stash = 16;
     const char *fz = std::getenv("IM_FUSE");
     pl->fuse = (fz && fz[0] == '0') ? 0 : 1;   // exchanges move 4-byte units
-    pl->pad2 = 0;
+    pl->leaf_shift = 0;
     pl->row_stride = row_bytes / key_size(key_dt);
     pl->rot_scale = row_bytes / 4;
     int64_t per = total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
@@ -266,6 +280,7 @@ bool make_plan_rows(DevState *ds, int key_dt, int64_t row_bytes, int ch, int64_t
     pl->cap_rot = pl->cap_nodes + 20 * per + 16;
     pl->cap_leaves = 1 + 6 * (int64_t)lv * per + 16;
     pl->cap_tiles = total / pl->tile + pl->cap_leaves + 16;
+    pl->leaf_shift = leaf_shift(*pl);
     return true;
 }
 
@@ -365,8 +380,8 @@ int read_error_bits(Counters *ctr, hipStream_t s, unsigned *bits) {
     return IM_OK;
 }
 
-// Everything up to the leaf merge: counters and roots, division levels,
-// leaf planning, tile co-ranks and dependencies.  `offs` is the caller's
+// Everything up to the leaf merge: counters and roots, division levels
+// (which also lay the leaves out in tiles), tile co-ranks and dependencies.  `offs` is the caller's
 // offsets or null for a single pair (la, lb).
 int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
                      int64_t n_inst, int64_t la, int64_t lb, const MlpDev *mlp, const Plan &pl,
@@ -395,9 +410,6 @@ int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *
         IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");
         prof_end(e1, kStRotate, 2, s);
     }
-    hipEvent_t e2 = prof ? prof_begin(s) : nullptr;
-    IM_HIP(launch_plan(pl, w, s), "launch plan");
-    prof_end(e2, kStPlan, 1, s);
     hipEvent_t e3 = prof ? prof_begin(s) : nullptr;
     IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
     IM_HIP(launch_tiledeps(pl, w, s), "launch tile dependencies");
@@ -415,7 +427,7 @@ void record_stats(const Plan &pl, const Work &w) {
     g_last_ctr = w.ctr;
 }
 
-// The whole merge: division levels, leaf planning, tile co-ranks, leaf merge.
+// The whole merge: division levels, tile co-ranks, leaf merge.
 // cfg_override >= 0 forces a leaf configuration (autotuner).
 // Rows mode of run_pipeline: row bytes (0: packed keys) and chunk bytes.
 struct RowsArg {
@@ -442,6 +454,8 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         if (!make_plan(ds, ek, ev, n_inst, total, max_inst, cfg, &pl))
             return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
     }
+    if (pl.leaf_shift == 0)
+        return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");
     pl.split_method = split_method;
     pl.rot_method = rot_method;
     if (split_method != kSplitCorank || rot_method != kRotLS) pl.fuse = 0;   // the paper's modes as such
@@ -922,6 +936,8 @@ int batched_inplace_merge_graph(im_graph **out, void *data, const int64_t *d_off
         if (!make_plan(ds, ek, 0, n, total_elems, max_instance, cfg, &pl))
             return fail(IM_ERR_HIP, "could not size the leaf merge grid");
     }
+    if (pl.leaf_shift == 0)
+        return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");
     pl.epoch = 1;   // every replay clears the flags first
     im_graph *g = new (std::nothrow) im_graph();
     if (!g) return fail(IM_ERR_WORKSPACE, "out of host memory");

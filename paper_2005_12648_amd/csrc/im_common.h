@@ -11,7 +11,8 @@
 //               k_rotate  - all exchanges of the level in one segmented
 //                           launch (phase A: block swap or the first two
 //                           reversals; phase B: the last reversal).
-//   k_plan      leaves -> workgroup tiles (prefix sum), barrier counters.
+//   (leaves get their tiles as they are emitted: one atomic on a packed
+//   leaf/tile counter gives each leaf its index and its first tile)
 //   k_tilerank  co-rank of every tile diagonal inside its leaf.
 //   k_leafmerge persistent kernel: each workgroup merges one tile in LDS; the
 //               tiles of one leaf meet at a per-leaf arrival counter between
@@ -83,6 +84,7 @@ struct Counters {
     unsigned long long split_fallbacks;  // FindMedian splits replaced by co-rank splits
     unsigned long long fused;            // nodes whose two levels ran as one exchange
     unsigned long long leaf_next;        // leaf merge: slots handed out beyond the static ones
+    unsigned long long leaf_tiles;       // (leaves << Plan::leaf_shift) | tiles, as emitted
     unsigned long long rot_next[kMaxLevels][2];  // exchanges: items handed out per level and phase
     unsigned int error;               // nonzero: a device-side check failed
     unsigned int pad;
@@ -121,7 +123,8 @@ struct Plan {
     int32_t rot_method;     // kRotLS or kRotCS
     int64_t cap_stash;      // circular shifting: stash slots per level
     int32_t fuse;           // fuse two division levels into one exchange where possible
-    int32_t pad2;
+    int32_t leaf_shift;     // bits of the tile count in the packed leaf/tile counter
+                            // (0: the caps do not fit in 64 bits; the plan is refused)
     // Rows (elements of several words ordered by their leading key): the
     // row length in key units (0: packed keys), and the number of 4-byte
     // exchange units per element (1: exchanges move whole elements).
@@ -168,7 +171,6 @@ hipError_t launch_split(int key, void *data, const int64_t *d_offsets, const Pla
                         const Work &w, int level, const MlpDev *mlp, hipStream_t s);
 hipError_t launch_rotate(int esize_k, int esize_v, void *keys, void *vals, const Plan &pl,
                          const Work &w, int level, int phase, hipStream_t s);
-hipError_t launch_plan(const Plan &pl, const Work &w, hipStream_t s);
 hipError_t launch_tilerank(int key, void *data, const int64_t *d_offsets, const Plan &pl,
                            const Work &w, const MlpDev *mlp, hipStream_t s);
 hipError_t launch_leafmerge(int key, int esize_v, void *keys, void *vals, const Plan &pl,

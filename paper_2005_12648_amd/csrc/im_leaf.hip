@@ -781,67 +781,6 @@ hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int6
     return hipErrorInvalidValue;
 }
 
-// ---- leaf planning: tiles per leaf, exclusive scan, barrier counters ----
-constexpr int kPlanThreads = 1024;
-
-__global__ __launch_bounds__(kPlanThreads) void k_plan(Plan pl, Work w) {
-    constexpr int kWaves = kPlanThreads / 64;
-    __shared__ long long s_wave[kWaves];
-    __shared__ unsigned long long s_elems;
-    int64_t L = (int64_t)w.ctr->leaves;
-    if (L > pl.cap_leaves) L = pl.cap_leaves;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0) s_elems = 0;
-    // each thread owns a contiguous run of leaves: tile counts and their sum
-    const int64_t per = (L + kPlanThreads - 1) / kPlanThreads;
-    const int64_t l0 = (int64_t)tid * per < L ? (int64_t)tid * per : L;
-    const int64_t l1 = l0 + per < L ? l0 + per : L;
-    long long sum = 0;
-    unsigned long long elems = 0;
-    for (int64_t l = l0; l < l1; ++l) {
-        const int64_t S = w.leaves[l].la + w.leaves[l].lb;
-        const long long c = (S + pl.tile - 1) / pl.tile;
-        w.leaves[l].ntiles = (int32_t)c;
-        elems += (unsigned long long)S;
-        sum += c;
-    }
-    // block-wide inclusive scan of the sums: in each wave, then of the waves
-    long long x = sum;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const long long y = __shfl(x, lane >= off ? lane - off : 0, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) s_wave[wid] = x;
-    __syncthreads();
-    if (wid == 0) {
-        long long v = lane < kWaves ? s_wave[lane] : 0;
-#pragma unroll
-        for (int off = 1; off < kWaves; off <<= 1) {
-            const long long y = __shfl(v, lane >= off ? lane - off : 0, 64);
-            if (lane >= off) v += y;
-        }
-        if (lane < kWaves) s_wave[lane] = v;
-    }
-    __syncthreads();
-    long long start = (x - sum) + (wid > 0 ? s_wave[wid - 1] : 0);
-    for (int64_t l = l0; l < l1; ++l) {
-        w.tile_start[l] = start;
-        start += w.leaves[l].ntiles;
-    }
-    if (elems) atomicAdd(&s_elems, elems);
-    __syncthreads();
-    if (tid == 0) {
-        w.ctr->leaf_elems = s_elems;
-        long long tot = s_wave[kWaves - 1];
-        if (tot > pl.cap_tiles) {
-            atomicOr(&w.ctr->error, kErrCapacity);
-            tot = pl.cap_tiles;
-        }
-        w.ctr->tiles = (unsigned long long)tot;
-    }
-}
-
 // Readers of each tile's window.  Tile i of a leaf (parts la, lb, size S)
 // writes [iT, min((i+1)T, S)).  The A elements there, [pa0, pa1) =
 // [iT, min((i+1)T, la)), are read by the tiles j whose A-slice
@@ -935,10 +874,6 @@ hipError_t launch_fill32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_plan(const Plan &pl, const Work &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, pl, w);
-    return hipGetLastError();
-}
 
 // ---- geometry and dispatch ----------------------------------------------
 // (key bytes, payload bytes, config) -> (threads, items per thread, depth).

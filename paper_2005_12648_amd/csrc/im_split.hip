@@ -134,20 +134,40 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
     }
 }
 
+// A leaf and its tiles: one atomic on the packed leaf/tile counter gives the
+// leaf its index and its first tile, so tile_start rises with the leaf index
+// (the tile co-rank kernel finds a tile's leaf by bisection) without a scan
+// over the leaves after the division.
 __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const Node &nd) {
-    unsigned long long slot = atomicAdd(&w.ctr->leaves, 1ull);
+    const int64_t S = nd.la + nd.lb;
+    const unsigned long long nt = (unsigned long long)((S + pl.tile - 1) / pl.tile);
+    const int sh = pl.leaf_shift;
+    const unsigned long long packed = atomicAdd(&w.ctr->leaf_tiles, (1ull << sh) + nt);
+    const unsigned long long slot = packed >> sh;
+    const unsigned long long tstart = packed & ((1ull << sh) - 1);
+    atomicAdd(&w.ctr->leaves, 1ull);
+    // The leaves below cap_leaves come first in the counter's order, and
+    // their tiles number at most total / tile + cap_leaves <= cap_tiles <
+    // 2^leaf_shift, so the two fields never carry into each other there.
+    // Only those leaves are counted in tiles and leaf_elems: the tile kernels
+    // never meet a tile of a dropped leaf.
     if ((int64_t)slot >= pl.cap_leaves) {
         atomicOr(&w.ctr->error, kErrCapacity);
         return;
     }
+    if ((int64_t)(tstart + nt) > pl.cap_tiles) atomicOr(&w.ctr->error, kErrCapacity);
+    atomicAdd(&w.ctr->tiles, nt);
+    atomicAdd(&w.ctr->leaf_elems, (unsigned long long)S);
     Leaf lf;
     lf.base = nd.base; lf.la = nd.la; lf.lb = nd.lb; lf.k0 = nd.k0; lf.i0 = nd.i0;
-    lf.inst = nd.inst; lf.ntiles = 0;
+    lf.inst = nd.inst;
+    lf.ntiles = (int32_t)nt;
     // direction of the tile order: the part that bounds how far elements
     // travel must be the one within leaf_span (see im_leaf.hip)
     lf.dir = (nd.la + nd.lb <= pl.leaf_cap || nd.lb <= pl.leaf_span) ? 0 : 1;
     lf.pad = 0;
     w.leaves[slot] = lf;
+    w.tile_start[slot] = (int64_t)tstart;
 }
 
 // Split node nd at (i, j): Alg. 3's "shift" exchanges A[i, la) and B[0, j),
