@@ -813,37 +813,32 @@ __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
             };
             const int64_t pa0 = i * T;
             const int64_t pa1 = (i + 1) * T < lf.la ? (i + 1) * T : lf.la;
-            if (pa0 < lf.la) {                       // window holds A elements
-                int64_t lo = 0, hi = nt - 1;         // ia(nt) = la > pa0
-                while (lo < hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (ia(mid + 1) > pa0) hi = mid; else lo = mid + 1;
-                }
-                alo = lo;
-                lo = 0; hi = nt - 1;                 // ia(0) = 0 < pa1
-                while (lo < hi) {
-                    int64_t mid = (lo + hi + 1) >> 1;
-                    if (ia(mid) < pa1) lo = mid; else hi = mid - 1;
-                }
-                ahi = lo;
-            }
             const int64_t e = (i + 1) * T < S ? (i + 1) * T : S;
-            if (e > lf.la) {                         // window holds B elements
-                const int64_t pb0 = (pa0 > lf.la ? pa0 : lf.la) - lf.la;
-                const int64_t pb1 = e - lf.la;
-                int64_t lo = 0, hi = nt - 1;         // jb(nt) = lb > pb0
-                while (lo < hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (jb(mid + 1) > pb0) hi = mid; else lo = mid + 1;
-                }
-                blo = lo;
-                lo = 0; hi = nt - 1;                 // jb(0) = 0 < pb1
-                while (lo < hi) {
-                    int64_t mid = (lo + hi + 1) >> 1;
-                    if (jb(mid) < pb1) lo = mid; else hi = mid - 1;
-                }
-                bhi = lo;
+            const int64_t pb0 = (pa0 > lf.la ? pa0 : lf.la) - lf.la;
+            const int64_t pb1 = e - lf.la;
+            const bool has_a = pa0 < lf.la;          // window holds A elements
+            const bool has_b = e > lf.la;            // window holds B elements
+            // The four bisections over [0, nt - 1] run side by side, so that
+            // each round issues its loads together:
+            //   0: first j with ia(j + 1) > pa0  (true at nt - 1: ia(nt) = la > pa0)
+            //   1: last j with ia(j) < pa1       (true at 0: ia(0) = 0 < pa1)
+            //   2: first j with jb(j + 1) > pb0  (true at nt - 1: jb(nt) = lb > pb0)
+            //   3: last j with jb(j) < pb1       (true at 0: jb(0) = 0 < pb1)
+            // A search whose part is absent starts empty (lo = hi).
+            int64_t lo0 = 0, hi0 = has_a ? nt - 1 : 0, lo1 = 0, hi1 = hi0;
+            int64_t lo2 = 0, hi2 = has_b ? nt - 1 : 0, lo3 = 0, hi3 = hi2;
+            while (lo0 < hi0 || lo1 < hi1 || lo2 < hi2 || lo3 < hi3) {
+                const int64_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1 + 1) >> 1;
+                const int64_t m2 = (lo2 + hi2) >> 1, m3 = (lo3 + hi3 + 1) >> 1;
+                // every index is in [0, nt]; ia(nt) needs no load
+                const int64_t v0 = ia(m0 + 1), v1 = ia(m1), v2 = jb(m2 + 1), v3 = jb(m3);
+                if (lo0 < hi0) { if (v0 > pa0) hi0 = m0; else lo0 = m0 + 1; }
+                if (lo1 < hi1) { if (v1 < pa1) lo1 = m1; else hi1 = m1 - 1; }
+                if (lo2 < hi2) { if (v2 > pb0) hi2 = m2; else lo2 = m2 + 1; }
+                if (lo3 < hi3) { if (v3 < pb1) lo3 = m3; else hi3 = m3 - 1; }
             }
+            if (has_a) { alo = lo0; ahi = lo1; }
+            if (has_b) { blo = lo2; bhi = lo3; }
         }
         w.tile_dep[4 * t] = (int32_t)alo;
         w.tile_dep[4 * t + 1] = (int32_t)ahi;

@@ -384,13 +384,15 @@ __device__ __forceinline__ void emit_node(const Plan &pl, const Work &w, int lev
 
 // What a child of a fused node does at the next level, read on the original
 // layout: 0 = nothing to split (empty part, in order, or a leaf), 1 = a
-// symmetric split (block swap), 2 = anything else (not fusable).
-template <typename KP>
-__device__ __forceinline__ int child_kind(const Plan &pl, KP A, int64_t la, KP B,
-                                          int64_t lb) {
+// symmetric split (block swap), 2 = anything else (not fusable).  The end
+// keys are loaded by the caller (both children's at once: one round of
+// loads instead of four dependent ones); an empty child's are not used.
+template <typename K>
+__device__ __forceinline__ int child_kind(const Plan &pl, int64_t la, int64_t lb, K a_first,
+                                          K a_last, K b_first, K b_last) {
     if (la == 0 || lb == 0) return 0;
-    if (A[la - 1] <= B[0]) return 0;
-    if (A[0] > B[lb - 1]) return 2;                    // a whole-child exchange
+    if (a_last <= b_first) return 0;
+    if (a_first > b_last) return 2;                    // a whole-child exchange
     if (la + lb <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) return 0;
     const int64_t S = la + lb, mx = la > lb ? la : lb;
     return (mx * 16 <= S * 9) ? 1 : 2;
@@ -437,11 +439,16 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
             const int64_t la = nd.la, lb = nd.lb;
             const KP A = data + nd.base;
             const KP B = A + la;
-            if (la == 0 || lb == 0) {
-                // nothing to merge
-            } else if (A[la - 1] <= B[0]) {
-                // already in order
-            } else if (A[0] > B[lb - 1] && level + 1 < pl.max_levels) {
+            // the four end keys in one round of loads
+            bool in_order = true, reversed = false;
+            if (la > 0 && lb > 0) {
+                const K a_first = A[0], a_last = A[la - 1], b_first = B[0], b_last = B[lb - 1];
+                in_order = a_last <= b_first;
+                reversed = a_first > b_last;
+            }
+            if (in_order) {
+                // nothing to merge (an empty part, or already in order)
+            } else if (reversed && level + 1 < pl.max_levels) {
                 // every B before every A: one exchange.  At the last level such
                 // a pair is merged as a leaf instead (every node there is within
                 // the leaf bounds), so that level never exchanges and its
@@ -505,8 +512,15 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
             if (may_fuse && kk == la && la - i > 0 && j > 0) {
                 // children on the original layout: L = A[0,i) | B[0,j),
                 // R = A[i,la) | B[j,lb)
-                const int kl = child_kind(pl, A, i, B, j);
-                const int kr = child_kind(pl, A + i, la - i, B + j, lb - j);
+                // children L = A[0,i) | B[0,j) and R = A[i,la) | B[j,lb): their
+                // end keys, with an empty part's indices moved to a key of the
+                // node (la, lb > 0; i < la here) so that every load is in range
+                const int64_t i1 = i > 0 ? i - 1 : 0, j1 = j > 0 ? j - 1 : 0;
+                const int64_t jx = j < lb ? j : lb - 1;
+                const K l_af = A[0], l_al = A[i1], l_bf = B[0], l_bl = B[j1];
+                const K r_af = A[i], r_al = A[la - 1], r_bf = B[jx], r_bl = B[lb - 1];
+                const int kl = child_kind(pl, i, j, l_af, l_al, l_bf, l_bl);
+                const int kr = child_kind(pl, la - i, lb - j, r_af, r_al, r_bf, r_bl);
                 if (kl != 2 && kr != 2) {
                     int64_t il = i, ir = la - i;          // kept whole: (|A_X|, |B_X|)
                     ++searches;
