@@ -192,3 +192,73 @@ def test_autotune_choice_is_used(dev):
     im.batched_inplace_merge(t, to)
     assert im.fetch_stats()["leaf_config"] == chosen
     check_batch(h(t), data, off, "tuned")
+
+
+# ------------------------------------------------------------ leaf counters
+def expected_leaves(data, off, tile, max_levels):
+    """Leaves, tiles and leaf elements that the instances fix when every one
+    is small enough to be a leaf at the first level: a pair with both parts
+    non-empty that is out of order is one leaf of ceil(S / tile) tiles, except
+    a pair with every B before every A, which is one exchange while a
+    further level exists."""
+    leaves = tiles = elems = 0
+    for q in range((off.size - 1) // 2):
+        o0, o1, o2 = off[2 * q], off[2 * q + 1], off[2 * q + 2]
+        a, b = data[o0:o1], data[o1:o2]
+        if a.size == 0 or b.size == 0 or a[-1] <= b[0]:
+            continue
+        if a[0] > b[-1] and max_levels > 1:
+            continue
+        s = int(o2 - o0)
+        leaves += 1
+        tiles += -(-s // tile)
+        elems += s
+    return leaves, tiles, elems
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_batched_leaf_counters(dev, leaf_cfg, cfg):
+    # leaves are laid out in tiles as the division emits them (one counter
+    # gives a leaf its index and its first tile): the counts must be exact
+    leaf_cfg(cfg)
+    rng = np.random.default_rng(501 + cfg)
+    n = 2500
+    sizes = rng.integers(0, 1500, size=2 * n)
+    sizes[rng.random(2 * n) < 0.05] = 0
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    data = rng.integers(0, 1 << 20, size=int(off[-1])).astype(np.int32)
+    kind = rng.integers(0, 8, size=n)
+    for q in range(n):
+        o0, o1, o2 = off[2 * q], off[2 * q + 1], off[2 * q + 2]
+        data[o0:o1].sort()
+        data[o1:o2].sort()
+        if kind[q] == 0:
+            data[o1:o2] += 1 << 21            # in order
+        elif kind[q] == 1:
+            data[o0:o1] += 1 << 21            # every B before every A
+    t, to = d(data, dev), d(off, dev)
+    say("leaf counters cfg", cfg, "instances", n, "elements", int(off[-1]))
+    im.batched_inplace_merge(t, to)
+    st = im.fetch_stats()
+    leaves, tiles, elems = expected_leaves(data, off, st["tile"], st["max_levels"])
+    assert (st["leaves"], st["tiles"], st["leaf_elems"]) == (leaves, tiles, elems), st
+    check_batch(h(t), data, off, "leaf counters")
+
+
+@pytest.mark.parametrize("tiles", [1, 3])
+def test_leaf_counters_bounds_several_levels(dev, leaf_tiles, tiles):
+    # several division levels: every leaf element is in one leaf, and the
+    # tiles are the leaves' ceil(S / tile): between leaf_elems / tile and
+    # that plus one per leaf
+    leaf_tiles(tiles)
+    la, lb = 1000003, 700001
+    data = gen.pair_uniform(la, lb, 97)
+    t = d(data, dev)
+    say("leaf counter bounds, leaf tiles", tiles)
+    im.inplace_merge(t, la)
+    st = im.fetch_stats()
+    assert st["levels_used"] >= 2, st
+    assert 0 < st["leaf_elems"] <= la + lb
+    lo = -(-st["leaf_elems"] // st["tile"])
+    assert lo <= st["tiles"] <= lo + st["leaves"] - 1, st
+    assert np.array_equal(h(t), oracle.merge(data, la))
