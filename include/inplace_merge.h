@@ -140,7 +140,10 @@ size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int k
  * total_elems: an upper bound of d_offsets[2n] (sizes the workspace).
  * max_instance: an upper bound of the largest instance (A+B) or 0 if unknown
  * (then total_elems is used); it sets how many division levels are enqueued.
- * Offsets are validated on the device only when IM_CHECK=1. */
+ * Offsets are validated on the device only when IM_CHECK=1.
+ * IM_ERR_INVALID_ARG if n >= 2^31, or if the leaf and tile capacities that n
+ * and total_elems imply do not fit together in one 64-bit device counter
+ * (only near 2^31 instances with several billion elements). */
 int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n,
                           int64_t total_elems, int64_t max_instance,
                           int dtype, hipStream_t stream);

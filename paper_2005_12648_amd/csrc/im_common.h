@@ -14,10 +14,11 @@
 //   (leaves get their tiles as they are emitted: one atomic on a packed
 //   leaf/tile counter gives each leaf its index and its first tile)
 //   k_tilerank  co-rank of every tile diagonal inside its leaf.
-//   k_leafmerge persistent kernel: each workgroup merges one tile in LDS; the
-//               tiles of one leaf meet at a per-leaf arrival counter between
-//               "all inputs read" and "outputs written" (Alg. 2/3 per-pair
-//               merge, several workgroups per pair).
+//   k_tiledeps  per tile: the range of tiles of its leaf that read its window.
+//   k_leafmerge persistent kernel: each workgroup merges tiles in LDS (Alg.
+//               2/3 per-pair merge, several workgroups per pair); a tile
+//               publishes "inputs read" once staged, and stores its output
+//               only after the tiles that read its window have published.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -95,7 +96,7 @@ constexpr unsigned long long kRotWorkMask = (1ull << kRotCountShift) - 1;
 
 // Error bits of Counters::error.
 constexpr unsigned kErrOversizeLeaf = 1u;   // a node still too large at the last level
-constexpr unsigned kErrBarrierSpin = 2u;    // per-leaf arrival wait gave up
+constexpr unsigned kErrBarrierSpin = 2u;    // a leaf-merge wait for readers' flags gave up
 constexpr unsigned kErrCapacity = 4u;       // a descriptor array overflowed
 constexpr unsigned kErrNotSorted = 8u;      // checked mode: a run is unsorted
 constexpr unsigned kErrOffsets = 16u;       // checked mode: offsets not monotone
