@@ -143,7 +143,7 @@ size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int k
  * Offsets are validated on the device only when IM_CHECK=1.
  * IM_ERR_INVALID_ARG if n >= 2^31, or if the leaf and tile capacities that n
  * and total_elems imply do not fit together in one 64-bit device counter
- * (only near 2^31 instances with several billion elements). */
+ * (only for n within a fraction of a percent of 2^31). */
 int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n,
                           int64_t total_elems, int64_t max_instance,
                           int dtype, hipStream_t stream);
