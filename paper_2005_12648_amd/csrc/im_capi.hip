@@ -381,8 +381,8 @@ int read_error_bits(Counters *ctr, hipStream_t s, unsigned *bits) {
 }
 
 // Everything up to the leaf merge: counters and roots, division levels
-// (which also lay the leaves out in tiles), tile co-ranks and dependencies.  `offs` is the caller's
-// offsets or null for a single pair (la, lb).
+// (which also lay the leaves out in tiles), tile co-ranks and dependencies.
+// `offs` is the caller's offsets or null for a single pair (la, lb).
 int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
                      int64_t n_inst, int64_t la, int64_t lb, const MlpDev *mlp, const Plan &pl,
                      const Work &w, bool check, bool prof, hipStream_t s) {

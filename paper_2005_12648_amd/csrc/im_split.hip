@@ -511,10 +511,9 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
             bool fused = false;
             if (may_fuse && kk == la && la - i > 0 && j > 0) {
                 // children on the original layout: L = A[0,i) | B[0,j),
-                // R = A[i,la) | B[j,lb)
-                // children L = A[0,i) | B[0,j) and R = A[i,la) | B[j,lb): their
-                // end keys, with an empty part's indices moved to a key of the
-                // node (la, lb > 0; i < la here) so that every load is in range
+                // R = A[i,la) | B[j,lb).  Their end keys, with an empty part's
+                // indices moved to a key of the node (la, lb > 0; i < la here)
+                // so that every load is in range
                 const int64_t i1 = i > 0 ? i - 1 : 0, j1 = j > 0 ? j - 1 : 0;
                 const int64_t jx = j < lb ? j : lb - 1;
                 const K l_af = A[0], l_al = A[i1], l_bf = B[0], l_bl = B[j1];
