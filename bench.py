@@ -291,6 +291,32 @@ def event_timed(torch, pristine, buf, fn, reps):
     return ts[len(ts) // 2]
 
 
+def bench_graph_single(torch, im, oracle, gen, dev, reps):
+    """The headline merge captured once as a one-instance graph and replayed
+    on fresh copies of its input, against the eager call on the same copies
+    (events around each call, copies outside)."""
+    la = lb = 2 ** 27
+    log("c2 graph: generating int32 2^27 + 2^27 on the device")
+    pristine = gen.torch_pair_uniform(la, lb, SEED + 20, dev)
+    buf = torch.empty_like(pristine)
+    off = torch.tensor([0, la, la + lb], dtype=torch.int64, device=dev)
+    want = oracle.merge(pristine.cpu().numpy(), la)
+    eager_ms = event_timed(torch, pristine, buf, lambda: im.inplace_merge(buf, la), reps)
+    bad_eager = mismatches(buf, want)
+    g = im.MergeGraph(buf, off)
+    try:
+        graph_ms = event_timed(torch, pristine, buf, g.launch, reps)
+    finally:
+        g.close()
+    bad_graph = mismatches(buf, want)
+    n = la + lb
+    return {"workload": "int32 2^27+2^27 (the headline input), one-instance captured graph",
+            "graph_ms": round(graph_ms, 4), "graph_gelem_s": round(n / graph_ms / 1e6, 2),
+            "eager_ms": round(eager_ms, 4), "eager_gelem_s": round(n / eager_ms / 1e6, 2),
+            "mismatches_graph": bad_graph, "mismatches_eager": bad_eager,
+            "timing": "median of %d calls, HIP events around each call" % reps}
+
+
 def bench_batched(torch, im, oracle, gen, dev, steps):
     log("c4: generating 4096 instances")
     data, off_d, off = gen.torch_batch(4096, SEED + 40, dev)
@@ -622,6 +648,8 @@ def main():
             log("variant", name)
             forms[name] = bench_variant(torch, im, oracle, gen, dev, name, 3)
             torch.cuda.empty_cache()
+        forms["c2_graph"] = bench_graph_single(torch, im, oracle, gen, dev, 7)
+        torch.cuda.empty_cache()
         forms["c4_batched"] = bench_batched(torch, im, oracle, gen, dev, 3)
         torch.cuda.empty_cache()
         forms["c4_sort"] = bench_sort(torch, im, oracle, gen, dev)
