@@ -616,8 +616,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU (the merge is measured on one "
-              "MI355X); --gpus %d / WORLD_SIZE=%d is not supported" % (args.gpus, world),
+        print("bench.py: the merge is measured on one GPU (one MI355X); "
+              "--gpus %d / WORLD_SIZE=%d is not supported" % (args.gpus, world),
               file=sys.stderr)
         sys.exit(2)
 
