@@ -55,7 +55,7 @@ def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with gcc (no HIP headers involved)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp],
+        subprocess.run(["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp],
                        check=True)
         os.replace(tmp, _LIB)
     return _LIB

@@ -35,18 +35,19 @@
  *
  *   - FindMedian (Sec. 3.3, Alg. 1): the paper's double binary search for
  *               a pivot pair that splits A and B into A0 A1, B0 B1 with
- *               A0 <= B1, B0 <= A1 and |A0|+|B0| close to |A1|+|B1|.  Taken
- *               step by step from Alg. 1; the loop as printed tests p_A, p_B
- *               before first setting them, and after a stop on an equal probe
- *               it recomputes midpoints (which can give an invalid split when
- *               keys repeat).  Reading used here: the probes start at the
- *               midpoints of A and B (the text of Sec. 3.3 says so), and a
- *               stop on an equal probe returns that probe pair.
+ *               A0 <= B1, B0 <= A1 and |A0|+|B0| close to |A1|+|B1|, written
+ *               from the moves Sec. 3.3 describes.  Where Alg. 1 is garbled
+ *               (its loop test reads p_A, p_B before they are first set, and
+ *               after a stop on equal values it recomputes middles, which can
+ *               give an invalid split when keys repeat) the reading used here
+ *               is: the indexes start at the middles of A and B (the text of
+ *               Sec. 3.3 says so), and a stop on equal values returns that
+ *               pair of indexes.
  *   - merge_par: the same stable merge computed by all host cores (OpenMP):
- *               the output is cut at equal ranks whose co-ranks come from one
- *               walk of the two-finger merge, each piece is merged into the
- *               fresh buffer, then copied back.  Only for timing beside the
- *               GPU; its result equals merge().
+ *               the output is cut at equal ranks, each thread bisects for the
+ *               co-rank of its own cut, merges its piece into the fresh
+ *               buffer, then the buffer is copied back.  Only for timing
+ *               beside the GPU; its result equals merge().
  *
  * Error behaviour: every function trusts its caller (the Python wrapper
  * validates shapes); on allocation failure the merge functions return -1.
@@ -229,37 +230,54 @@ int orc_rotate_cs(int64_t *data, int64_t la, int64_t lb,
 }
 
 /* ------------------------------------------------------------------------ */
-/* FindMedian (Sec. 3.3, Alg. 1), with the reading stated at the top.       */
+/* FindMedian (Sec. 3.3, Alg. 1).  The pivot pair (p_A, p_B) cuts A into    */
+/* A0 = A[0,p_A), A1 = A[p_A,L_A) and B into B0, B1 so that A0 <= B1 and     */
+/* B0 <= A1 (Sec. 3.3), while |A0|+|B0| stays close to |A1|+|B1|.  It is a   */
+/* double binary search: p_A and p_B each search a window [lo, hi) of their  */
+/* run and sit at its middle.  After each look at A[p_A] and B[p_B] one      */
+/* window shrinks, toward balance (Sec. 3.3):                                */
+/*   - when the parts below the pivots are the smaller ones                  */
+/*     (|A0|+|B0| < |A1|+|B1|), the index whose value is the smaller moves   */
+/*     up (its window starts after it);                                      */
+/*   - otherwise the index whose value is the larger moves down (its window  */
+/*     ends at it).                                                          */
+/* Equal values count as "A's value is the larger".  The search ends when a  */
+/* window is empty (each index then takes its window's middle), or, reading */
+/* stated at the top, on a look at two equal values: that pair is a valid    */
+/* pivot by itself (A0 <= v <= B1 and B0 <= v <= A1 for the common value v). */
+/* The runs placed entirely in order, or entirely reversed, are recognised  */
+/* first (the two tests that open Alg. 1).                                   */
 /* ------------------------------------------------------------------------ */
 #define DEFINE_FIND_MEDIAN(NAME, KT)                                           \
 void NAME(const KT *A, int64_t la, const KT *B, int64_t lb,                     \
           int64_t *pa_out, int64_t *pb_out)                                     \
 {                                                                               \
-    /* special cases tested first (Alg. 1, first two tests) */                 \
-    if (la == 0 || lb == 0 || A[la - 1] <= B[0]) {                              \
+    if (la == 0 || lb == 0 || A[la - 1] <= B[0]) {   /* A already below B */    \
         *pa_out = la; *pb_out = 0; return;                                      \
     }                                                                           \
-    if (!(A[0] <= B[lb - 1])) { *pa_out = 0; *pb_out = lb; return; }            \
-    int64_t left_a = 0, limit_a = la, left_b = 0, limit_b = lb;                 \
-    int64_t p_a = la / 2, p_b = lb / 2;     /* probes start at the middles */   \
-    while (left_a < limit_a && left_b < limit_b && A[p_a] != B[p_b]) {          \
-        p_a = (limit_a - left_a) / 2 + left_a;                                  \
-        p_b = (limit_b - left_b) / 2 + left_b;                                  \
-        int64_t a0 = p_a, a1 = la - p_a, b0 = p_b, b1 = lb - p_b;               \
-        if (A[p_a] < B[p_b]) {                                                  \
-            if (a0 + b0 < a1 + b1) left_a = p_a + 1;                            \
-            else limit_b = p_b;                                                 \
+    if (!(A[0] <= B[lb - 1])) {                      /* A entirely above B */   \
+        *pa_out = 0; *pb_out = lb; return;                                      \
+    }                                                                           \
+    int64_t a_lo = 0, a_hi = la, b_lo = 0, b_hi = lb;                           \
+    int64_t p_A = la / 2, p_B = lb / 2;               /* the two middles */     \
+    if (A[p_A] == B[p_B]) { *pa_out = p_A; *pb_out = p_B; return; }             \
+    for (;;) {                                                                  \
+        int below_smaller = p_A + p_B < (la - p_A) + (lb - p_B);                \
+        int a_value_smaller = A[p_A] < B[p_B];                                  \
+        if (below_smaller) {                                                    \
+            if (a_value_smaller) a_lo = p_A + 1; else b_lo = p_B + 1;           \
         } else {                                                                \
-            if (a0 + b0 < a1 + b1) left_b = p_b + 1;                            \
-            else limit_a = p_a;                                                 \
+            if (a_value_smaller) b_hi = p_B; else a_hi = p_A;                   \
         }                                                                       \
+        if (a_lo >= a_hi || b_lo >= b_hi) break;     /* a window is empty */    \
+        if (A[p_A] == B[p_B]) {                      /* equal look: a pivot */  \
+            *pa_out = p_A; *pb_out = p_B; return;                               \
+        }                                                                       \
+        p_A = a_lo + (a_hi - a_lo) / 2;                                         \
+        p_B = b_lo + (b_hi - b_lo) / 2;                                         \
     }                                                                           \
-    if (left_a < limit_a && left_b < limit_b) {                                 \
-        /* stopped because A[p_a] == B[p_b]: that probe pair is the pivot */    \
-        *pa_out = p_a; *pb_out = p_b; return;                                   \
-    }                                                                           \
-    *pa_out = (limit_a - left_a) / 2 + left_a;                                  \
-    *pb_out = (limit_b - left_b) / 2 + left_b;                                  \
+    *pa_out = a_lo + (a_hi - a_lo) / 2;                                         \
+    *pb_out = b_lo + (b_hi - b_lo) / 2;                                         \
 }
 
 DEFINE_FIND_MEDIAN(orc_find_median_i32, int32_t)
@@ -268,12 +286,25 @@ DEFINE_FIND_MEDIAN(orc_find_median_i64, int64_t)
 DEFINE_FIND_MEDIAN(orc_find_median_u64, uint64_t)
 
 /* ------------------------------------------------------------------------ */
-/* All-cores stable merge (timing only): cuts at ranks k_t = t*N/P, co-ranks */
-/* from one walk of the two-finger merge, pieces merged in parallel into a   */
-/* fresh buffer, parallel copy back.  Returns the threads used, -1 on        */
+/* All-cores stable merge (timing only).  Output rank k_t = t*N/P starts     */
+/* thread t's piece; the thread finds the co-rank of k_t itself by bisection */
+/* on the predicate A[m] <= B[k-1-m] (true, then false, over the admissible  */
+/* m: the first false m is the number of A elements among the first k_t     */
+/* outputs when ties take A), merges its piece into a fresh buffer, and the  */
+/* buffer is copied back in parallel.  Returns the threads used, -1 on       */
 /* allocation failure.                                                       */
 /* ------------------------------------------------------------------------ */
 #define DEFINE_MERGE_PAR(NAME, KT)                                             \
+static int64_t NAME##_cut(const KT *A, int64_t la, const KT *B, int64_t lb,    \
+                          int64_t k)                                            \
+{                                                                               \
+    int64_t lo = k > lb ? k - lb : 0, hi = k < la ? k : la;                     \
+    while (lo < hi) {                                                           \
+        int64_t m = lo + (hi - lo) / 2;                                         \
+        if (A[m] <= B[k - 1 - m]) lo = m + 1; else hi = m;                      \
+    }                                                                           \
+    return lo;                                                                  \
+}                                                                               \
 int NAME(KT *data, int64_t la, int64_t lb)                                      \
 {                                                                               \
     int64_t n = la + lb;                                                        \
@@ -281,24 +312,14 @@ int NAME(KT *data, int64_t la, int64_t lb)                                      
     _Pragma("omp parallel") { _Pragma("omp single") P = OMP_THREADS(); }       \
     if (n == 0) return P;                                                       \
     KT *out = (KT *)malloc((size_t)n * sizeof(KT));                             \
-    int64_t *ia = (int64_t *)malloc((size_t)(P + 1) * sizeof(int64_t));        \
-    if (!out || !ia) { free(out); free(ia); return -1; }                        \
+    if (!out) return -1;                                                        \
     const KT *A = data, *B = data + la;                                         \
-    /* one walk of the merge gives the co-rank of every cut */                  \
-    int64_t i = 0, j = 0;                                                       \
-    for (int t = 0; t <= P; t++) {                                              \
-        int64_t k = (int64_t)((double)n * t / P);                               \
-        if (t == P) k = n;                                                      \
-        while (i + j < k) {                                                     \
-            if (j >= lb || (i < la && A[i] <= B[j])) i++; else j++;             \
-        }                                                                       \
-        ia[t] = i;                                                              \
-    }                                                                           \
     _Pragma("omp parallel for schedule(static)")                                \
     for (int t = 0; t < P; t++) {                                               \
         int64_t k0 = (int64_t)((double)n * t / P);                              \
         int64_t k1 = (t + 1 == P) ? n : (int64_t)((double)n * (t + 1) / P);     \
-        int64_t x = ia[t], y = k0 - ia[t], o = k0;                              \
+        int64_t x = NAME##_cut(A, la, B, lb, k0);                               \
+        int64_t y = k0 - x, o = k0;                                             \
         while (o < k1) {                                                        \
             if (y >= lb || (x < la && A[x] <= B[y])) out[o++] = A[x++];         \
             else out[o++] = B[y++];                                             \
@@ -306,7 +327,7 @@ int NAME(KT *data, int64_t la, int64_t lb)                                      
     }                                                                           \
     _Pragma("omp parallel for schedule(static)")                                \
     for (int64_t q = 0; q < n; q++) data[q] = out[q];                           \
-    free(out); free(ia);                                                        \
+    free(out);                                                                  \
     return P;                                                                   \
 }
 

@@ -337,6 +337,12 @@ def test_merge_par_equals_merge():
         got, threads = oracle.merge_par(d, la)
         assert threads >= 1
         assert np.array_equal(got, oracle.merge(d, la))
+    # cuts that fall inside runs of equal keys, and every B before every A:
+    # each thread's own bisection must agree with the stable order
+    for d, la in [(np.zeros(100003, np.int64), 50000),
+                  (np.concatenate([np.arange(5000, 9000), np.arange(0, 5000)]).astype(np.int64), 4000)]:
+        got, _ = oracle.merge_par(d, la)
+        assert np.array_equal(got, oracle.merge(d, la))
 
 
 @pytest.mark.parametrize("dt", [np.int32, np.uint32, np.int64, np.uint64])
