@@ -224,8 +224,10 @@ def bench_headline(torch, im, oracle, gen, dev, args):
         cpu = {"value": round(n / med_p / 1e9, 4), "unit": "Gelem/s",
                "cores": par_out["threads"], "kind": "oracle",
                "sample": "full workload (int32 2^27+2^27), %d repetitions, median; the "
-                         "oracle's all-cores stable merge (OpenMP: cuts at equal ranks, "
-                         "pieces merged into a fresh buffer, copied back)" % reps_p,
+                         "oracle's all-cores stable merge (OpenMP: cuts at equal output "
+                         "ranks, each thread bisects its own cut's co-rank and merges its "
+                         "piece into a fresh buffer, parallel copy back; -O3)" % reps_p,
+               "speedup_over_single_thread": round(med_s / med_p, 2),
                "single_thread_value": round(n / med_s / 1e9, 4),
                "single_thread_sample": "%d repetitions, median; two-finger merge into a "
                                        "fresh buffer + copy back" % reps,
@@ -393,7 +395,7 @@ def bench_learned(torch, im, oracle, gen, dev, steps):
     pristine = gen.torch_pair_learned(la, lb, SEED + 50, dev)
     model = im.MergeModel(seed=SEED)
     t0 = time.perf_counter()
-    model.train(pristine, la, samples=8192, steps=1500, lr=3e-3)
+    model.train(pristine, la, samples=8192, steps=20000, lr=1e-2)
     train_s = time.perf_counter() - t0
     k = min(steps, 4)
     fn_l = lambda b: model.merge(b, la)
@@ -406,11 +408,11 @@ def bench_learned(torch, im, oracle, gen, dev, steps):
         fn(buf)
     torch.cuda.synchronize()
     rounds_l, rounds_p = [], []
-    for _ in range(3):
+    for _ in range(5):
         rounds_l.append(timed_merges(torch, im, pristine, la, k, 0, fn=fn_l)[0])
         rounds_p.append(timed_merges(torch, im, pristine, la, k, 0, fn=fn_p)[0])
-    ms_l = sorted(rounds_l)[1]
-    ms_p = sorted(rounds_p)[1]
+    ms_l = sorted(rounds_l)[2]
+    ms_p = sorted(rounds_p)[2]
     del buf
     _, prof_l, bufs = timed_merges(torch, im, pristine, la, k, 0, fn=fn_l, profile=True)
     st_l = im.fetch_stats()
@@ -436,7 +438,7 @@ def bench_learned(torch, im, oracle, gen, dev, steps):
             "probes_per_search_plain": round(st_p["search_probes"] / max(st_p["searches"], 1), 2),
             "probes_per_diagonal_learned_65537": round(float(probes_l.double().mean()), 2),
             "probes_per_diagonal_plain_65537": round(float(probes_p.double().mean()), 2),
-            "timing": "median of 3 alternating rounds of %d merges per form, after a warm-up "
+            "timing": "median of 5 alternating rounds of %d merges per form, after a warm-up "
                       "merge of each" % k,
             "rounds_ms_learned": [round(x, 4) for x in rounds_l],
             "rounds_ms_plain": [round(x, 4) for x in rounds_p],
@@ -485,7 +487,7 @@ def bench_findmedian(torch, im, gen, dev, steps):
     for name, split in (("corank", im.SPLIT_CORANK), ("findmedian", im.SPLIT_FINDMEDIAN)):
         ms, _, bufs = timed_merges(torch, im, pristine, la, steps, 1,
                                    fn=lambda b: im.inplace_merge_variant(b, la, split,
-                                                                         im.ROTATE_LS))
+                                                                         im.ROTATE_SWAP_REV))
         st = im.fetch_stats()
         res[name] = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
                      "levels_used": st["levels_used"], "leaves": st["leaves"],
@@ -494,7 +496,7 @@ def bench_findmedian(torch, im, gen, dev, steps):
     same = True
     a = pristine.clone()
     b = pristine.clone()
-    im.inplace_merge_variant(a, la, im.SPLIT_FINDMEDIAN, im.ROTATE_LS)
+    im.inplace_merge_variant(a, la, im.SPLIT_FINDMEDIAN, im.ROTATE_SWAP_REV)
     im.inplace_merge(b, la)
     same = bool(torch.equal(a, b))
     log("f2: findmedian merge %.3f ms, corank %.3f ms" % (res["findmedian"]["ms"],
@@ -518,12 +520,23 @@ def bench_exchanges(torch, im, oracle, gen, dev, steps):
     for label, lx in (("swap 2^27|2^27", n // 2), ("2^27+3|2^27-3", n // 2 + 3),
                       ("2^24|rest", 2 ** 24)):
         buf = x.clone()
-        ms_ls = event_timed(torch, x, buf, lambda: im.rotate(buf, lx), max(steps, 3))
+        # the merge's exchange: one block swap when the parts are equal, else
+        # three reversals; the paper's linear shifting step by step; circular
+        # shifting
+        ms_sr = event_timed(torch, x, buf, lambda: im.rotate(buf, lx), max(steps, 3))
+        ms_ls = event_timed(torch, x, buf, lambda: im.rotate_ls(buf, lx, count=False),
+                            max(steps, 3))
         ms_cs = event_timed(torch, x, buf, lambda: im.rotate_cs(buf, lx), max(steps, 3))
+        buf.copy_(x)
+        _, swaps = im.rotate_ls(buf, lx)
+        ok = bool(torch.equal(buf[:n - lx], x[lx:]) and torch.equal(buf[n - lx:], x[:lx]))
         moved = 2 * 4 * n          # every element read and written once (definition)
-        out[label] = {"ls_ms": round(ms_ls, 4), "cs_ms": round(ms_cs, 4),
+        out[label] = {"swap_rev_ms": round(ms_sr, 4), "ls_ms": round(ms_ls, 4),
+                      "cs_ms": round(ms_cs, 4),
+                      "swap_rev_eff_gb_s": round(moved / ms_sr / 1e6, 1),
                       "ls_eff_gb_s": round(moved / ms_ls / 1e6, 1),
-                      "cs_eff_gb_s": round(moved / ms_cs / 1e6, 1)}
+                      "cs_eff_gb_s": round(moved / ms_cs / 1e6, 1),
+                      "ls_swaps": swaps, "ls_correct": ok}
         del buf
     del x
     torch.cuda.empty_cache()
@@ -531,7 +544,7 @@ def bench_exchanges(torch, im, oracle, gen, dev, steps):
     pristine = gen.torch_pair_uniform(la, lb, SEED + 20, dev)
     merges = {}
     for name, fn in (
-            ("in_place_ls", lambda b: im.inplace_merge(b, la)),
+            ("in_place_swap_rev", lambda b: im.inplace_merge(b, la)),
             ("in_place_cs", lambda b: im.inplace_merge_variant(b, la, im.SPLIT_CORANK,
                                                                im.ROTATE_CS)),
             ("buffered_alloc_merge_copy_free", lambda b: im.inplace_merge_buffered(b, la))):
@@ -605,8 +618,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--forms", choices=["all", "none", "rows"], default="all",
-                    help="other workloads after the headline: all, none, or only the rows form")
+    ap.add_argument("--forms", choices=["all", "none", "rows", "learned", "exchanges"],
+                    default="all",
+                    help="other workloads after the headline: all, none, or only the rows, "
+                         "the learned-split or the exchange forms")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (profiling runs: default leaf configuration)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -663,6 +678,10 @@ def main():
         forms["f4_wide_rows"] = bench_rows(torch, im, oracle, gen, dev, 3)
     elif args.forms == "rows":
         forms["f4_wide_rows"] = bench_rows(torch, im, oracle, gen, dev, 3)
+    elif args.forms == "learned":
+        forms["c5_learned"] = bench_learned(torch, im, oracle, gen, dev, args.steps)
+    elif args.forms == "exchanges":
+        forms["f3_exchange_and_out_of_place"] = bench_exchanges(torch, im, oracle, gen, dev, 3)
     st = head["stats"]
     line = {
         "metric": "Gelem/s, in-place merge of int32 L_A=L_B=2^27",

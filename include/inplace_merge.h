@@ -16,8 +16,9 @@
  *    retains them after the call returns.
  *  - Work is enqueued on `stream` and is asynchronous: a return value of 0
  *    means "validated and enqueued", not "finished".  Kernel faults surface at
- *    the caller's next synchronisation.  A NULL stream means the default
- *    stream.
+ *    the caller's next synchronisation; device-side error bits through
+ *    inplace_merge_device_status() (see there).  A NULL stream means the
+ *    default stream.
  *  - The result is the STABLE merge: equal keys keep A before B and keep their
  *    order inside a run (the paper does not discuss ties; this is the reading
  *    of the per-pair std::inplace_merge, which is stable).
@@ -29,6 +30,9 @@
  *  - Return value: IM_OK (0) or a negative IM_ERR_* code.  Nothing throws
  *    across this boundary.  inplace_merge_last_error() returns a thread-local
  *    description of the last failure on the calling thread.
+ *  - The merge entry points refuse a stream that is capturing a graph
+ *    (IM_ERR_INVALID_ARG): a captured call would replay this call's flag
+ *    epoch and workspace.  batched_inplace_merge_graph records a merge.
  *  - Concurrent calls on different streams of the same device share the
  *    library's workspace only through a per-device lock: they are safe but
  *    serialised at enqueue time; the enqueued work itself may overlap only if
@@ -63,7 +67,7 @@ enum {
     IM_ERR_WORKSPACE = -4,         /* workspace too small / allocation failed */
     IM_ERR_NOT_SORTED = -5,        /* IM_CHECK=1 and an input run is unsorted */
     IM_ERR_UNIMPLEMENTED = -6,
-    IM_ERR_DEVICE = -7             /* a device-side bounded wait gave up      */
+    IM_ERR_DEVICE = -7             /* a kernel raised a device-side error bit */
 };
 
 /* Statistics of the most recent merge enqueued by the calling thread.
@@ -120,9 +124,12 @@ int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B,
  * exchanges move 4-byte words); the leaves gather rows into registers in
  * merged order.  Requirements (else IM_ERR_INVALID_ARG): row_bytes a
  * multiple of 4 and of the key size; data aligned to the key size; at most
- * 65536 bytes per row when row_bytes is a multiple of 16 and data is
- * 16-byte aligned, 32768 when a multiple of 8, 16384 otherwise.  IM_CHECK=1
- * checks the runs' keys.  The element counts of im_stats count rows. */
+ * 81920 bytes per row, which admits the paper's largest element (a 4-byte
+ * key and 16384 ints, 65540 bytes).  Rows move in 16-, 8- or 4-byte chunks
+ * (the widest that divides the row and the address; rows above 64 KiB move
+ * in 4-byte chunks).
+ * IM_CHECK=1 checks the runs' keys.  The element counts of im_stats count
+ * rows. */
 int inplace_merge_rows(void *data, int64_t L_A, int64_t L_B, int64_t row_bytes,
                        int key_dtype, hipStream_t stream);
 
@@ -137,20 +144,28 @@ size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int k
 /* d_offsets: device int64[2n+1], non-decreasing.  Instance q has
  *   A = data[d_offsets[2q],   d_offsets[2q+1])
  *   B = data[d_offsets[2q+1], d_offsets[2q+2]).
+ * The library reads d_offsets[2n] back to size its workspace: one 8-byte
+ * copy on `stream` and a synchronisation of it (the _sized form below is
+ * fully asynchronous).  Offsets are validated on the device only when
+ * IM_CHECK=1.  IM_ERR_INVALID_ARG if n >= 2^31 or the stream is capturing. */
+int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n, int dtype,
+                          hipStream_t stream);
+int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
+                             int key_dtype, int val_dtype, hipStream_t stream);
+
+/* The same merges without a synchronisation: the caller states the sizes.
  * total_elems: an upper bound of d_offsets[2n] (sizes the workspace).
  * max_instance: an upper bound of the largest instance (A+B) or 0 if unknown
  * (then total_elems is used); it sets how many division levels are enqueued.
- * Offsets are validated on the device only when IM_CHECK=1.
  * IM_ERR_INVALID_ARG if n >= 2^31, or if the leaf and tile capacities that n
  * and total_elems imply do not fit together in one 64-bit device counter
  * (only for n within a fraction of a percent of 2^31). */
-int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n,
-                          int64_t total_elems, int64_t max_instance,
-                          int dtype, hipStream_t stream);
-
-int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
-                             int64_t total_elems, int64_t max_instance,
-                             int key_dtype, int val_dtype, hipStream_t stream);
+int batched_inplace_merge_sized(void *data, const int64_t *d_offsets, int64_t n,
+                                int64_t total_elems, int64_t max_instance, int dtype,
+                                hipStream_t stream);
+int batched_inplace_merge_kv_sized(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
+                                   int64_t total_elems, int64_t max_instance, int key_dtype,
+                                   int val_dtype, hipStream_t stream);
 
 /* ---------------------------------------------------------------------- */
 /* Captured batched merge: the whole launch sequence of one batched merge  */
@@ -215,7 +230,8 @@ int inplace_merge_autotune(const void *data, const int64_t *d_offsets, int64_t n
 /* ---------------------------------------------------------------------- */
 #define IM_SPLIT_CORANK 0      /* exact co-rank split (Sec. 3.1, "optimal")      */
 #define IM_SPLIT_FINDMEDIAN 1  /* FindMedian double binary search (Alg. 1)     */
-#define IM_ROTATE_LS 0         /* linear shifting: block swap / reversals       */
+#define IM_ROTATE_SWAP_REV 0   /* one block swap (a linear-shifting step) when   */
+                               /* the parts are equal, else three reversals       */
 #define IM_ROTATE_CS 1         /* circular shifting: cycles (Sec. 3.4)          */
 
 /* inplace_merge() with the split and exchange methods chosen (keys only).
@@ -245,6 +261,22 @@ int im_divide(const void *data, int64_t L_A, int64_t L_B, int dtype, int method,
  * comparator of im_rotate.  elem_bytes 4 or 8; stream-ordered stash. */
 int im_rotate_cs(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t stream);
 
+/* Partition exchange X|Y -> Y|X by linear shifting, step by step (Sec. 3.4):
+ * the smaller block is swapped with the block at the far end of the larger
+ * one, which puts it in its final place, and the same is done on what
+ * remains, until one part is empty.  Performs exactly the paper's element
+ * swaps, L - gcd(lx, ly) of them for L = lx + ly (Sec. 3.5 counts up to
+ * 2L).  The steps that keep the same smaller block (one quotient of
+ * Euclid's algorithm on the two lengths) run as one launch, one lane per
+ * column of the block and segment of its chain of swaps; such a column's
+ * value between two swaps stays in a register, so the fixed block is
+ * written once per run.  d_swaps (device int64, may be NULL) receives the
+ * element swaps the kernels performed.  elem_bytes 4 or 8; uses a
+ * stream-ordered stash of about 2L/256 elements when a run's chains are
+ * longer than 256 swaps. */
+int im_rotate_ls(void *data, int64_t lx, int64_t ly, int elem_bytes, int64_t *d_swaps,
+                 hipStream_t stream);
+
 /* The classic out-of-place merge (the paper's external-buffer comparator):
  * out = stable merge of in[0,L_A) and in[L_A,L_A+L_B); in and out must not
  * overlap.  inplace_merge_buffered() allocates the buffer, merges into it,
@@ -263,11 +295,18 @@ int inplace_merge_sort(void *data, int64_t n, int dtype, hipStream_t stream);
 /* Workspace, errors, statistics.                                          */
 /* ---------------------------------------------------------------------- */
 
-/* Bytes of device workspace a merge of `total_elems` elements in `n_inst`
- * instances needs (the library allocates it lazily per device if none is
- * set).  The workspace holds split descriptors and counters only: its size
- * grows with the number of workgroup tiles, never with the data itself. */
-size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dtype);
+/* Bytes of device workspace that any single merge of N elements of this
+ * dtype needs (keys, key+payload, every leaf configuration, and the passes
+ * of an in-place merge sort of N).  The library allocates its workspace
+ * lazily per device if none is set.  The workspace holds split descriptors
+ * and counters only: its size grows with the number of workgroup tiles,
+ * never with the data itself (about 0.3 MB for 2^28 int32 elements).
+ * Returns 0 for invalid arguments. */
+size_t inplace_merge_workspace_bytes(int64_t N, int dtype);
+
+/* The same for a batched merge of `total_elems` elements in `n_inst`
+ * instances (the descriptor arrays grow with the instance count). */
+size_t inplace_merge_workspace_bytes_batched(int64_t total_elems, int64_t n_inst, int dtype);
 
 /* Use caller-owned device memory as the workspace of the current device
  * (NULL/0 returns to library-owned workspace).  The caller keeps ownership
@@ -277,8 +316,30 @@ int inplace_merge_set_workspace(void *d_ws, size_t bytes);
 const char *inplace_merge_last_error(void);
 
 /* Copy the statistics of the last enqueued merge of this thread into *out.
- * Synchronises `stream` to read the device counters. */
+ * Synchronises `stream` to read the device counters.  Returns IM_ERR_DEVICE
+ * if that merge raised a device-side error bit. */
 int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream);
+
+/* The same, synchronising the stream the last merge of this thread was
+ * enqueued on. */
+typedef im_stats merge_stats;
+int inplace_merge_last_stats(merge_stats *out);
+
+/* How a device-side failure reaches the caller.  An enqueued merge returns
+ * IM_OK once validated and enqueued; the kernels that run later can still
+ * fail in three ways, each of which leaves the data a permutation of the
+ * input but not merged: a node still larger than a leaf at the last division
+ * level (error bit 1), a bounded wait for another workgroup's flag that gave
+ * up (bit 2), a descriptor array that overflowed (bit 4).  The kernel that
+ * raises a bit also stores it into a word of pinned host memory owned by
+ * the library (one per device).  inplace_merge_device_status() reads and
+ * clears that word WITHOUT synchronising anything: it returns IM_ERR_DEVICE
+ * (message: the bit) if any merge enqueued on the current device has raised
+ * a bit that completed since the last query, else IM_OK.  Call it after the
+ * caller's own synchronisation to learn about every merge before it.  The
+ * same bits are returned by inplace_merge_fetch_stats / _last_stats for the
+ * last merge, and by the merge itself under IM_CHECK=1. */
+int inplace_merge_device_status(void);
 
 /* Stage timing for the calling thread.  While enabled, every merge records
  * HIP events on its stream around its launch groups; _read synchronises
@@ -311,9 +372,12 @@ int im_rotate(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t st
 
 /* ---------------------------------------------------------------------- */
 /* Learned split: a 1->H->1 ReLU network (H = 32, fp32) predicts co-ranks;  */
-/* an exponential-then-binary search always corrects the prediction to the */
-/* exact co-rank, so results are identical to inplace_merge().              */
-/* Not part of the paper.                                                   */
+/* a search corrects every prediction to the exact co-rank, so results are */
+/* identical to inplace_merge().  The search starts from a bracket around  */
+/* the prediction (half-width from the model's error table), checks both   */
+/* ends, gallops outward (doubling steps) from an end that fails, and      */
+/* bisects inside; where the bracket is not clearly narrower than the      */
+/* plain search range it is a plain search.  Not part of the paper.        */
 /* ---------------------------------------------------------------------- */
 typedef struct merge_model merge_model;
 
@@ -332,10 +396,18 @@ typedef struct {
 int merge_model_create(merge_model **m, const float *params, uint64_t seed);
 
 /* Train on the GPU: labels are produced by the plain co-rank search at
- * `samples` evenly spaced diagonals of the given runs, then `steps` Adam
- * steps run with the library's forward/backward/update kernels.
- * Synchronises `stream` at the end (the model lives on the device). */
-int merge_model_train(merge_model *m, const void *data, int64_t L_A, int64_t L_B,
+ * `samples` evenly spaced diagonals k_p = floor((p + 1/2) N / samples) of
+ * the given runs (x = k_p/N, target i(k_p)/L_A, both rounded to fp32), then
+ * `steps` Adam steps run with the library's forward/backward/update kernels,
+ * the learning rate decaying from cfg->lr to zero on a cosine
+ * (lr_s = lr (1 + cos(pi s / steps)) / 2 at step s).  Last, the model's
+ * error table is measured on the same diagonals: per bucket of x (128
+ * buckets), the half-width of the bracket its searches start from.  If *m is
+ * NULL a model is first created from cfg->seed (and freed again, *m reset
+ * to NULL, if training fails); otherwise the model *m is trained further
+ * (its Adam moments restart at zero).  Synchronises `stream` at the end
+ * (the model lives on the device). */
+int merge_model_train(merge_model **m, const void *data, int64_t L_A, int64_t L_B,
                       int dtype, const merge_train_cfg *cfg, hipStream_t stream);
 
 /* One forward+backward pass of the mean squared error on device samples
@@ -348,9 +420,19 @@ int merge_model_grad(const merge_model *m, const float *d_x, const float *d_t, i
 int merge_model_forward(const merge_model *m, const float *d_x, int64_t M, float *d_y,
                         hipStream_t stream);
 
-/* Host copy of the parameters / replace them. */
+/* Host copy of the parameters / replace them.  Replacing them forgets the
+ * model's error table: its searches are plain binary searches until it is
+ * trained again (results are exact either way). */
 int merge_model_get_params(const merge_model *m, float *params_out);
 int merge_model_set_params(merge_model *m, const float *params);
+
+/* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected, `step` counting from 1) of the model's device parameters with
+ * the device gradient d_grad[IM_MLP_PARAMS]; the moments d_m, d_v
+ * (device, IM_MLP_PARAMS floats each, zero before step 1) are updated in
+ * place.  The same kernel runs every step of merge_model_train. */
+int merge_model_adam_step(merge_model *m, const float *d_grad, float *d_m, float *d_v, float lr,
+                          int step, hipStream_t stream);
 
 /* Learned-split co-rank of diagonals d_k[0..nk): same result as im_corank;
  * d_probes (optional, may be NULL) receives the probes spent per diagonal. */

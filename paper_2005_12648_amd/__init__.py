@@ -27,8 +27,8 @@ __all__ = [
     "MergeModel", "MLP_HIDDEN", "MLP_PARAMS", "profile", "profile_read", "STAGES",
     "MergeGraph", "set_config", "autotune", "LEAF_CONFIGS",
     "inplace_merge_variant", "divide", "rotate_cs", "merge_out_of_place",
-    "inplace_merge_buffered", "SPLIT_CORANK", "SPLIT_FINDMEDIAN", "ROTATE_LS", "ROTATE_CS",
-    "inplace_merge_rows", "rows_workspace_bytes",
+    "inplace_merge_buffered", "SPLIT_CORANK", "SPLIT_FINDMEDIAN", "ROTATE_SWAP_REV", "ROTATE_CS",
+    "inplace_merge_rows", "rows_workspace_bytes", "last_stats", "device_status", "rotate_ls",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +39,9 @@ MLP_HIDDEN = 32
 MLP_PARAMS = 3 * MLP_HIDDEN + 1
 LEAF_CONFIGS = 4
 SPLIT_CORANK, SPLIT_FINDMEDIAN = 0, 1
-ROTATE_LS, ROTATE_CS = 0, 1
+ROTATE_SWAP_REV, ROTATE_CS = 0, 1
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DTYPE, ERR_HIP = 0, -1, -2, -3
+ERR_WORKSPACE, ERR_NOT_SORTED, ERR_UNIMPLEMENTED, ERR_DEVICE = -4, -5, -6, -7
 
 # im_dtype codes of the C ABI
 _DT = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3}
@@ -96,18 +98,23 @@ def load():
         "inplace_merge": [vp, i64, i64, c_int, vp],
         "inplace_merge_kv": [vp, vp, i64, i64, c_int, c_int, vp],
         "inplace_merge_rows": [vp, i64, i64, i64, c_int, vp],
-        "batched_inplace_merge": [vp, vp, i64, i64, i64, c_int, vp],
-        "batched_inplace_merge_kv": [vp, vp, vp, i64, i64, i64, c_int, c_int, vp],
+        "batched_inplace_merge": [vp, vp, i64, c_int, vp],
+        "batched_inplace_merge_kv": [vp, vp, vp, i64, c_int, c_int, vp],
+        "batched_inplace_merge_sized": [vp, vp, i64, i64, i64, c_int, vp],
+        "batched_inplace_merge_kv_sized": [vp, vp, vp, i64, i64, i64, c_int, c_int, vp],
         "inplace_merge_sort": [vp, i64, c_int, vp],
         "inplace_merge_set_workspace": [vp, ctypes.c_size_t],
         "inplace_merge_fetch_stats": [ctypes.POINTER(_Stats), vp],
+        "inplace_merge_last_stats": [ctypes.POINTER(_Stats)],
+        "inplace_merge_device_status": [],
         "im_corank": [vp, i64, i64, c_int, vp, i64, vp, vp, vp],
         "im_rotate": [vp, i64, i64, c_int, vp],
         "merge_model_create": [ctypes.POINTER(vp), vp, ctypes.c_uint64],
-        "merge_model_train": [vp, vp, i64, i64, c_int, ctypes.POINTER(_TrainCfg), vp],
+        "merge_model_train": [ctypes.POINTER(vp), vp, i64, i64, c_int, ctypes.POINTER(_TrainCfg), vp],
         "merge_model_grad": [vp, vp, vp, i64, vp, vp, vp],
         "merge_model_forward": [vp, vp, i64, vp, vp],
         "merge_model_get_params": [vp, vp],
+        "merge_model_adam_step": [vp, vp, vp, vp, ctypes.c_float, c_int, vp],
         "merge_model_set_params": [vp, vp],
         "im_corank_learned": [vp, i64, i64, c_int, vp, vp, i64, vp, vp, vp],
         "inplace_merge_learned": [vp, i64, i64, c_int, vp, vp],
@@ -124,6 +131,7 @@ def load():
         "inplace_merge_variant": [vp, i64, i64, c_int, c_int, c_int, vp],
         "im_divide": [vp, i64, i64, c_int, c_int, c_int, vp, vp],
         "im_rotate_cs": [vp, i64, i64, c_int, vp],
+        "im_rotate_ls": [vp, i64, i64, c_int, vp, vp],
         "merge_out_of_place": [vp, vp, i64, i64, c_int, vp],
         "inplace_merge_buffered": [vp, i64, i64, c_int, vp],
         "inplace_merge_autotune": [vp, vp, i64, i64, i64, c_int, c_int, c_int,
@@ -133,8 +141,10 @@ def load():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = c_int
-    lib.inplace_merge_workspace_bytes.argtypes = [i64, i64, c_int]
+    lib.inplace_merge_workspace_bytes.argtypes = [i64, c_int]
     lib.inplace_merge_workspace_bytes.restype = ctypes.c_size_t
+    lib.inplace_merge_workspace_bytes_batched.argtypes = [i64, i64, c_int]
+    lib.inplace_merge_workspace_bytes_batched.restype = ctypes.c_size_t
     lib.inplace_merge_rows_workspace_bytes.argtypes = [i64, i64, c_int]
     lib.inplace_merge_rows_workspace_bytes.restype = ctypes.c_size_t
     lib.inplace_merge_last_error.argtypes = []
@@ -223,22 +233,31 @@ def rows_workspace_bytes(rows: int, row_bytes: int, key_dtype=torch.int32) -> in
 
 
 def batched_inplace_merge(data: torch.Tensor, offsets: torch.Tensor, max_instance: int = 0,
-                          stream=None) -> torch.Tensor:
-    """offsets: device int64[2n+1]; instance q merges [o[2q],o[2q+1]) with [o[2q+1],o[2q+2])."""
+                          stream=None, sized: bool = True) -> torch.Tensor:
+    """offsets: device int64[2n+1]; instance q merges [o[2q],o[2q+1]) with [o[2q+1],o[2q+2]).
+
+    sized=True calls batched_inplace_merge_sized with total = data.numel()
+    (asynchronous); sized=False calls batched_inplace_merge, which reads the
+    total back from the offsets (one synchronisation)."""
     _dev_tensor(data, "data")
     _dev_tensor(offsets, "offsets")
     if offsets.dtype != torch.int64 or offsets.numel() < 1 or offsets.numel() % 2 != 1:
         raise ValueError("offsets must be int64 with 2n+1 entries")
     n = (offsets.numel() - 1) // 2
     with torch.cuda.device(data.device):
-        _check(load().batched_inplace_merge(ctypes.c_void_p(data.data_ptr()),
-                                            ctypes.c_void_p(offsets.data_ptr()), n, data.numel(),
-                                            max_instance, _key_code(data), _stream(stream)))
+        if sized:
+            _check(load().batched_inplace_merge_sized(
+                ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+                data.numel(), max_instance, _key_code(data), _stream(stream)))
+        else:
+            _check(load().batched_inplace_merge(
+                ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+                _key_code(data), _stream(stream)))
     return data
 
 
 def batched_inplace_merge_kv(keys: torch.Tensor, vals: torch.Tensor, offsets: torch.Tensor,
-                             max_instance: int = 0, stream=None):
+                             max_instance: int = 0, stream=None, sized: bool = True):
     _dev_tensor(keys, "keys")
     _dev_tensor(vals, "vals")
     _dev_tensor(offsets, "offsets")
@@ -248,10 +267,16 @@ def batched_inplace_merge_kv(keys: torch.Tensor, vals: torch.Tensor, offsets: to
         raise ValueError("shape mismatch")
     n = (offsets.numel() - 1) // 2
     with torch.cuda.device(keys.device):
-        _check(load().batched_inplace_merge_kv(
-            ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
-            ctypes.c_void_p(offsets.data_ptr()), n, keys.numel(), max_instance,
-            _key_code(keys), _key_code(vals), _stream(stream)))
+        if sized:
+            _check(load().batched_inplace_merge_kv_sized(
+                ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                ctypes.c_void_p(offsets.data_ptr()), n, keys.numel(), max_instance,
+                _key_code(keys), _key_code(vals), _stream(stream)))
+        else:
+            _check(load().batched_inplace_merge_kv(
+                ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                ctypes.c_void_p(offsets.data_ptr()), n, _key_code(keys), _key_code(vals),
+                _stream(stream)))
     return keys, vals
 
 
@@ -297,7 +322,7 @@ def rotate(data: torch.Tensor, lx: int, stream=None) -> torch.Tensor:
 
 
 def inplace_merge_variant(data: torch.Tensor, la: int, split: int = SPLIT_CORANK,
-                          rotation: int = ROTATE_LS, stream=None) -> torch.Tensor:
+                          rotation: int = ROTATE_SWAP_REV, stream=None) -> torch.Tensor:
     """In-place merge with the split (co-rank / FindMedian) and exchange (linear /
     circular shifting) methods of the paper chosen; keys only."""
     _dev_tensor(data, "data")
@@ -339,6 +364,24 @@ def rotate_cs(data: torch.Tensor, lx: int, stream=None) -> torch.Tensor:
     return data
 
 
+def rotate_ls(data: torch.Tensor, lx: int, stream=None, count: bool = True):
+    """Partition exchange by linear shifting, step by step (the paper's swaps):
+    data = X|Y becomes Y|X.  Returns (data, element swaps counted on the
+    device, read after a synchronisation of the stream), or (data, None)
+    with count=False (no count, no synchronisation)."""
+    _dev_tensor(data, "data")
+    n = data.numel()
+    if not 0 <= lx <= n:
+        raise ValueError("lx out of range")
+    swaps = torch.zeros(1, dtype=torch.int64, device=data.device) if count else None
+    with torch.cuda.device(data.device):
+        _check(load().im_rotate_ls(ctypes.c_void_p(data.data_ptr()), lx, n - lx,
+                                   data.element_size(),
+                                   ctypes.c_void_p(swaps.data_ptr()) if count else None,
+                                   _stream(stream)))
+    return data, (int(swaps.item()) if count else None)
+
+
 def merge_out_of_place(data: torch.Tensor, la: int, out: Optional[torch.Tensor] = None,
                        stream=None) -> torch.Tensor:
     """Stable merge of data[:la] and data[la:] into a separate tensor."""
@@ -377,6 +420,22 @@ def fetch_stats(stream=None) -> dict:
     return {f: getattr(st, f) for f, _ in _Stats._fields_}
 
 
+def last_stats() -> dict:
+    """Statistics of the last merge of this thread (synchronises the stream it ran on)."""
+    st = _Stats()
+    _check(load().inplace_merge_last_stats(ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+
+def device_status(device=None) -> int:
+    """Device-side error bits raised since the last query on this device, read
+    without a synchronisation: raises IMError(ERR_DEVICE) if any, else 0."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    with torch.cuda.device(dev):
+        _check(load().inplace_merge_device_status())
+    return 0
+
+
 STAGES = ("split", "rotate", "plan", "tilerank", "leafmerge")
 
 
@@ -394,7 +453,11 @@ def profile_read(stream=None) -> dict:
 
 
 def workspace_bytes(total_elems: int, n_inst: int, dtype: torch.dtype) -> int:
-    return int(load().inplace_merge_workspace_bytes(total_elems, n_inst, _DT[dtype]))
+    """Workspace bytes of a merge of total_elems elements in n_inst instances
+    (n_inst == 1: any single merge or merge sort of that length)."""
+    if n_inst == 1:
+        return int(load().inplace_merge_workspace_bytes(total_elems, _DT[dtype]))
+    return int(load().inplace_merge_workspace_bytes_batched(total_elems, n_inst, _DT[dtype]))
 
 
 def set_workspace(buf: Optional[torch.Tensor]):
@@ -527,8 +590,8 @@ class MergeModel:
         _dev_tensor(data, "data")
         cfg = _TrainCfg(samples, steps, lr, seed)
         with torch.cuda.device(data.device):
-            _check(load().merge_model_train(self._h, ctypes.c_void_p(data.data_ptr()), la,
-                                            data.numel() - la, _key_code(data),
+            _check(load().merge_model_train(ctypes.byref(self._h), ctypes.c_void_p(data.data_ptr()),
+                                            la, data.numel() - la, _key_code(data),
                                             ctypes.byref(cfg), _stream(stream)))
         return self
 
@@ -544,6 +607,20 @@ class MergeModel:
                                            ctypes.c_void_p(g.data_ptr()),
                                            ctypes.c_void_p(loss.data_ptr()), _stream(stream)))
         return g, loss
+
+    def adam_step(self, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float, step: int,
+                  stream=None):
+        """One Adam step of the device parameters with device gradient g; the
+        moments m, v (device fp32, MLP_PARAMS each) are updated in place."""
+        for t, name in ((g, "g"), (m, "m"), (v, "v")):
+            _dev_tensor(t, name)
+            if t.dtype != torch.float32 or t.numel() != MLP_PARAMS:
+                raise ValueError("%s must be float32 with %d entries" % (name, MLP_PARAMS))
+        with torch.cuda.device(g.device):
+            _check(load().merge_model_adam_step(self._h, ctypes.c_void_p(g.data_ptr()),
+                                                ctypes.c_void_p(m.data_ptr()),
+                                                ctypes.c_void_p(v.data_ptr()), float(lr),
+                                                int(step), _stream(stream)))
 
     def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
         _dev_tensor(x, "x")

@@ -22,6 +22,7 @@ namespace {
 thread_local std::string g_err = "";
 thread_local im_stats g_stats = {};
 thread_local Counters *g_last_ctr = nullptr;
+thread_local hipStream_t g_last_stream = nullptr;
 
 // Stage timing (inplace_merge_profile): events recorded on the caller's
 // stream around each group of launches, read back by
@@ -100,13 +101,17 @@ struct DevState {
     // Autotuned leaf configuration by (key 4/8, payload 0/4/8, floor(log2 of
     // the mean instance size)); -1: not tuned.
     int tuned[2][3][64];
-    int64_t *sort_off = nullptr; // offsets of the merge-sort passes
-    int64_t sort_off_cap = 0;
+    // Host-memory word (pinned, mapped) that kernels raise error bits into
+    // (Work::host_err); read without a synchronisation.
+    unsigned *h_err = nullptr;
+    unsigned *d_err = nullptr;
+    bool err_tried = false;
     // Tile flags sit right after the counters.  flag_cap flags there are
     // known to hold only values < epoch (zeroed, or written by earlier
     // calls); the rest of the layout always starts after them.
     int64_t flag_cap = 0;
     uint32_t epoch = 0;
+    std::string cache_path;      // the IM_AUTOTUNE_CACHE file last read for this device
     DevState() {
         for (auto &a : tuned)
             for (auto &b : a)
@@ -115,6 +120,7 @@ struct DevState {
 };
 
 std::atomic<int> g_force_cfg{-1};   // inplace_merge_set_config
+
 
 int size_class(int64_t n_inst, int64_t total) {
     int64_t mean = total / std::max<int64_t>(n_inst, 1);
@@ -126,11 +132,46 @@ int size_class(int64_t n_inst, int64_t total) {
 int key_index(int ek) { return ek == 4 ? 0 : 1; }
 int val_index(int ev) { return ev == 0 ? 0 : (ev == 4 ? 1 : 2); }
 
-// Leaf configuration of a run: forced, else tuned for the class, else 0.
+// IM_LOG: 0 (default) silent; 1 one line per merge call (its plan); 2 also
+// the autotuner's timings and the tune cache.
+int log_level() {
+    const char *v = std::getenv("IM_LOG");
+    return v ? (int)std::strtol(v, nullptr, 10) : 0;
+}
+
+// IM_TILE (elements per leaf tile) and IM_WAVES (wavefronts per leaf
+// workgroup) pick the first leaf configuration that matches both for the
+// element sizes of the call, overriding the tuned table; -1 if unset or if
+// no configuration matches (then a line is logged at IM_LOG >= 1).
+int env_cfg(int ek, int ev) {
+    const char *te = std::getenv("IM_TILE"), *we = std::getenv("IM_WAVES");
+    if (!te && !we) return -1;
+    const long tile = te ? std::strtol(te, nullptr, 10) : -1;
+    const long waves = we ? std::strtol(we, nullptr, 10) : -1;
+    for (int c = 0; c < kLeafCfgs; ++c) {
+        int th, ipt, depth;
+        size_t lds;
+        leaf_geometry(ek, ev, c, &th, &ipt, &depth, &lds);
+        if ((tile < 0 || tile == (long)th * ipt) && (waves < 0 || waves == th / 64)) return c;
+    }
+    if (log_level() >= 1)
+        std::fprintf(stderr, "[inplace_merge] IM_TILE=%s IM_WAVES=%s match no leaf configuration "
+                             "for %d-byte keys and %d-byte payloads; ignored\n",
+                     te ? te : "-", we ? we : "-", ek, ev);
+    return -1;
+}
+
+void load_tune_cache(DevState *ds, int dev);
+
+// Leaf configuration of a run: forced, else IM_TILE / IM_WAVES, else tuned
+// for the class (this process's autotuner runs, or the IM_AUTOTUNE_CACHE
+// file), else 0.
 int choose_cfg(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int override_cfg) {
     if (override_cfg >= 0 && override_cfg < kLeafCfgs) return override_cfg;
     int f = g_force_cfg.load();
     if (f >= 0 && f < kLeafCfgs) return f;
+    const int e = env_cfg(ek, ev);
+    if (e >= 0) return e;
     int t = ds->tuned[key_index(ek)][val_index(ev)][size_class(n_inst, total)];
     return (t >= 0 && t < kLeafCfgs) ? t : 0;
 }
@@ -142,6 +183,57 @@ DevState *dev_state(int *dev_out) {
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     if (dev_out) *dev_out = dev;
     return &g_dev[dev];
+}
+
+// The on-disk tune cache (IM_AUTOTUNE_CACHE=<path>): one line per tuned
+// workload class, "imtune1 <gcn arch> <key bytes> <payload bytes> <class>
+// <config>"; later lines win.  Read by a device's first merge after the
+// variable names a file it has not read; the autotuner appends its result.
+// Lines of other architectures, and malformed lines, are skipped.
+std::string device_arch(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    for (char &c : a)
+        if (c == ' ' || c == '\n' || c == '\t') c = '_';
+    return a.empty() ? "unknown" : a;
+}
+
+void load_tune_cache(DevState *ds, int dev) {
+    const char *path = std::getenv("IM_AUTOTUNE_CACHE");
+    if (!path || !*path || ds->cache_path == path) return;
+    ds->cache_path = path;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    const std::string arch = device_arch(dev);
+    char tag[32], a[128];
+    int ek, ev, cls, cfg, loaded = 0;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::sscanf(line, "%31s %127s %d %d %d %d", tag, a, &ek, &ev, &cls, &cfg) != 6) continue;
+        if (std::strcmp(tag, "imtune1") != 0 || arch != a) continue;
+        if ((ek != 4 && ek != 8) || (ev != 0 && ev != 4 && ev != 8) || cls < 0 || cls >= 64 ||
+            cfg < 0 || cfg >= kLeafCfgs)
+            continue;
+        ds->tuned[key_index(ek)][val_index(ev)][cls] = cfg;
+        ++loaded;
+    }
+    std::fclose(f);
+    if (log_level() >= 2)
+        std::fprintf(stderr, "[inplace_merge] tune cache %s: %d entries for %s\n", path, loaded,
+                     arch.c_str());
+}
+
+void save_tune_entry(int dev, int ek, int ev, int cls, int cfg) {
+    const char *path = std::getenv("IM_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) {
+        if (log_level() >= 1) std::fprintf(stderr, "[inplace_merge] cannot append to %s\n", path);
+        return;
+    }
+    std::fprintf(f, "imtune1 %s %d %d %d %d\n", device_arch(dev).c_str(), ek, ev, cls, cfg);
+    std::fclose(f);
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -206,7 +298,7 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     }
     pl->max_levels = lv;
     pl->split_method = kSplitCorank;
-    pl->rot_method = kRotLS;
+    pl->rot_method = kRotSwapRev;
     pl->cap_stash = 2 * (total / kCsSeg) + 16;
     // Two division levels are fused into one exchange where the splits are
     // symmetric (k_split); the rotation kernel cycles up to kMaxCyc pieces
@@ -216,6 +308,7 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->leaf_shift = 0;
     pl->row_stride = 0;
     pl->rot_scale = 1;
+    pl->sort_width = 0;
     // A node is split only when it exceeds the leaf capacity, so a level has
     // fewer than `per` split nodes; a level's node list takes children of
     // the level before (2 per split) and grandchildren of fused nodes two
@@ -268,13 +361,14 @@ bool make_plan_rows(DevState *ds, int key_dt, int64_t row_bytes, int ch, int64_t
     }
     pl->max_levels = lv;
     pl->split_method = kSplitCorank;
-    pl->rot_method = kRotLS;
+    pl->rot_method = kRotSwapRev;
     pl->cap_stash = 16;
     const char *fz = std::getenv("IM_FUSE");
     pl->fuse = (fz && fz[0] == '0') ? 0 : 1;   // exchanges move 4-byte units
     pl->leaf_shift = 0;
     pl->row_stride = row_bytes / key_size(key_dt);
     pl->rot_scale = row_bytes / 4;
+    pl->sort_width = 0;
     int64_t per = total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
     pl->cap_nodes = std::max<int64_t>(1, 6 * per) + 16;
     pl->cap_rot = pl->cap_nodes + 20 * per + 16;
@@ -306,6 +400,9 @@ size_t carve(const Plan &pl, int64_t flag_slots, void *base, Work *w) {
     x.offsets1 = (int64_t *)take(sizeof(int64_t) * 4);
     x.cs_stash_k = nullptr;
     x.cs_stash_v = nullptr;
+    x.sort_off = pl.sort_width > 0 ? (int64_t *)take(sizeof(int64_t) * (2 * pl.n_inst + 1))
+                                   : nullptr;
+    x.host_err = nullptr;
     if (pl.rot_method == kRotCS) {
         x.cs_stash_k = take((size_t)8 * pl.cap_stash);
         x.cs_stash_v = take((size_t)8 * pl.cap_stash);
@@ -345,6 +442,28 @@ int acquire_ws(DevState *ds, size_t need, void **out) {
     }
     *out = ds->ws;
     return IM_OK;
+}
+
+// The host word of the device's error bits (allocated once; null if pinned
+// memory is unavailable, and errors then reach the host only through the
+// counters).
+void ensure_err_word(DevState *ds) {
+    if (ds->err_tried) return;
+    ds->err_tried = true;
+    void *h = nullptr;
+    if (hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        return;
+    }
+    std::memset(h, 0, 256);
+    ds->h_err = (unsigned *)h;
+    ds->d_err = (unsigned *)d;
 }
 
 bool stream_capturing(hipStream_t s) {
@@ -435,17 +554,28 @@ struct RowsArg {
     int ch;
 };
 
+// sort_width > 0: a merge-sort pass over runs of that width (its offsets are
+// written into the workspace, in stream order after the workspace's earlier
+// users; d_offsets is then ignored).
 int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_offsets,
                  int64_t n_inst, int64_t total, int64_t max_inst, int64_t la, int64_t lb,
                  const MlpDev *mlp, hipStream_t s, int cfg_override = -1,
-                 int split_method = kSplitCorank, int rot_method = kRotLS,
-                 RowsArg rows = RowsArg{0, 0}) {
+                 int split_method = kSplitCorank, int rot_method = kRotSwapRev,
+                 RowsArg rows = RowsArg{0, 0}, int64_t sort_width = 0) {
     int dev = 0;
     DevState *ds = dev_state(&dev);
     if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    // A captured call would bake this call's epoch and workspace into the
+    // graph: later replays would find every tile flag already set.  Graphs
+    // are recorded by batched_inplace_merge_graph, which owns its workspace.
+    if (stream_capturing(s))
+        return fail(IM_ERR_INVALID_ARG, "the stream is capturing a graph: record the merge "
+                                        "with batched_inplace_merge_graph instead");
     std::lock_guard<std::mutex> lock(ds->mu);
+    ensure_err_word(ds);
+    load_tune_cache(ds, dev);
     const int ek = key_size(key_dt);
-    Plan pl;
+    Plan pl = {};
     if (rows.bytes > 0) {
         if (!make_plan_rows(ds, key_dt, rows.bytes, rows.ch, total, &pl))
             return fail(IM_ERR_HIP, "could not size the rows leaf merge grid");
@@ -458,49 +588,84 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");
     pl.split_method = split_method;
     pl.rot_method = rot_method;
-    if (split_method != kSplitCorank || rot_method != kRotLS) pl.fuse = 0;   // the paper's modes as such
-    size_t need = carve(pl, ds->flag_cap, nullptr, nullptr);
+    pl.sort_width = sort_width;
+    if (split_method != kSplitCorank || rot_method != kRotSwapRev) pl.fuse = 0;   // the paper's modes as such
+    int64_t &flag_cap = ds->flag_cap;
+    uint32_t &epoch = ds->epoch;
+    size_t need = carve(pl, flag_cap, nullptr, nullptr);
     void *base = nullptr;
     int rc = acquire_ws(ds, need, &base);
     if (rc) return rc;
-    if (carve(pl, ds->flag_cap, nullptr, nullptr) > need) {
+    if (carve(pl, flag_cap, nullptr, nullptr) > need) {
         // the buffer was replaced (flag_cap reset): size again
-        need = carve(pl, ds->flag_cap, nullptr, nullptr);
+        need = carve(pl, flag_cap, nullptr, nullptr);
         rc = acquire_ws(ds, need, &base);
         if (rc) return rc;
     }
     Work w;
-    carve(pl, ds->flag_cap, base, &w);
+    carve(pl, flag_cap, base, &w);
+    w.host_err = ds->d_err;
     rc = ws_enter(ds, s);
     if (rc) return rc;
+    if (sort_width > 0) {
+        IM_HIP(launch_pass_offsets(total, sort_width, w.sort_off, n_inst, s), "launch pass offsets");
+        d_offsets = w.sort_off;
+    }
     // Tile flags: a tile is "read" when its flag equals this call's epoch.
     // Flags beyond flag_cap may hold stale data of other arrays, so they are
     // cleared (with a kernel: graph-capture safe) before first use.
-    if (pl.cap_tiles > ds->flag_cap || ds->epoch == 0xFFFFFFFFu) {
-        int64_t nflags = std::max<int64_t>(ds->flag_cap, pl.cap_tiles);
+    if (pl.cap_tiles > flag_cap || epoch == 0xFFFFFFFFu) {
+        int64_t nflags = std::max<int64_t>(flag_cap, pl.cap_tiles);
         IM_HIP(launch_fill32(w.tile_flag, nflags, 0u, s), "clear tile flags");
-        ds->flag_cap = nflags;
-        if (ds->epoch == 0xFFFFFFFFu) ds->epoch = 0;
+        flag_cap = nflags;
+        if (epoch == 0xFFFFFFFFu) epoch = 0;
     }
-    pl.epoch = ++ds->epoch;
+    pl.epoch = ++epoch;
 
     const bool check = checked_mode();
     if (std::getenv("IM_FAULT") && std::strcmp(std::getenv("IM_FAULT"), "launch") == 0)
         return fail(IM_ERR_HIP, "kernel launch failed (injected)");
-    const bool prof = g_prof && !stream_capturing(s);
-    rc = enqueue_division(key_dt, ev, keys, vals, d_offsets, n_inst, la, lb, mlp, pl, w, check,
-                          prof, s);
-    if (rc) return rc;
-    hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
-    if (rows.bytes > 0)
-        IM_HIP(launch_leafrows(key_dt, rows.ch, keys, rows.bytes, pl, w, s), "launch rows merge");
-    else
-        IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
-    prof_end(e4, kStLeafMerge, 1, s);
+    const bool prof = g_prof;
+    // A single small pair: one launch (im_leaf.hip, k_smallmerge) when it has
+    // at most a quarter of the resident tiles.  Not in checked mode, for the
+    // paper's split and exchange modes, for the learned split (its searches
+    // are the point there), or under the test hooks that force division
+    // levels or a small grid; IM_SMALL=0 turns it off.
+    const char *sm = std::getenv("IM_SMALL");
+    const bool small = !(sm && sm[0] == '0') && n_inst == 1 && d_offsets == nullptr &&
+                       rows.bytes == 0 && mlp == nullptr && sort_width == 0 && !check &&
+                       split_method == kSplitCorank && rot_method == kRotSwapRev && pl.cfg == 0 &&
+                       !std::getenv("IM_LEAF_TILES") && !std::getenv("IM_LEAF_GRID") &&
+                       (total + pl.tile - 1) / pl.tile <= pl.grid_leaf / 4;
+    if (small) {
+        hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
+        IM_HIP(launch_smallmerge(key_dt, ev, keys, vals, la, lb, pl, w, s), "launch small merge");
+        prof_end(e4, kStLeafMerge, 1, s);
+    } else {
+        rc = enqueue_division(key_dt, ev, keys, vals, d_offsets, n_inst, la, lb, mlp, pl, w, check,
+                              prof, s);
+        if (rc) return rc;
+        hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
+        if (rows.bytes > 0)
+            IM_HIP(launch_leafrows(key_dt, rows.ch, keys, rows.bytes, pl, w, s), "launch rows merge");
+        else
+            IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
+        prof_end(e4, kStLeafMerge, 1, s);
+    }
     rc = ws_leave(ds, s);
     if (rc) return rc;
 
     record_stats(pl, w);
+    g_last_stream = s;
+    if (log_level() >= 1)
+        std::fprintf(stderr,
+                     "[inplace_merge] dev %d: %lld instance(s), %lld elements, key %d B, payload "
+                     "%d B%s; leaf config %d (tile %lld, grid %d), leaf capacity %lld, span %lld, "
+                     "%d level(s) enqueued, fusion %s, workspace %zu B%s\n",
+                     dev, (long long)n_inst, (long long)total, ek, ev,
+                     rows.bytes > 0 ? " (rows)" : "", pl.cfg, (long long)pl.tile, pl.grid_leaf,
+                     (long long)pl.leaf_cap, (long long)pl.leaf_span, pl.max_levels,
+                     pl.fuse ? "on" : "off", need, small ? ", one launch" : "");
     if (check) {
         unsigned bits = 0;
         rc = read_error_bits(w.ctr, s, &bits);
@@ -543,6 +708,10 @@ struct merge_model {
     float *d_v = nullptr;
     float host[kMlpParams] = {};
     float err_scale = 1.0f;
+    float err_b[kErrBuckets];    // bracket half-widths (kErrUnknown: untrained)
+    merge_model() {
+        for (float &v : err_b) v = kErrUnknown;
+    }
 };
 
 static uint64_t splitmix(uint64_t &s) {
@@ -557,6 +726,7 @@ static int model_upload(merge_model *m) {
     std::memset(&h, 0, sizeof(h));
     std::memcpy(h.p, m->host, sizeof(m->host));
     h.err_scale = m->err_scale;
+    std::memcpy(h.err_b, m->err_b, sizeof(m->err_b));
     IM_HIP(hipMemcpy(m->d, &h, sizeof(h), hipMemcpyHostToDevice), "model upload");
     return IM_OK;
 }
@@ -597,12 +767,13 @@ static int rows_chunk(const void *data, int64_t row_bytes, int key_dtype, const 
         *why = "data must be aligned to the key size";
         return 0;
     }
+    // the widest chunk that divides the row and the address and still puts
+    // a whole row in a tile
     int ch = 4;
-    if (row_bytes % 16 == 0 && a % 16 == 0) ch = 16;
-    else if (row_bytes % 8 == 0 && a % 8 == 0) ch = 8;
+    if (row_bytes % 16 == 0 && a % 16 == 0 && rows_tile(row_bytes, 16) >= 1) ch = 16;
+    else if (row_bytes % 8 == 0 && a % 8 == 0 && rows_tile(row_bytes, 8) >= 1) ch = 8;
     if (rows_tile(row_bytes, ch) < 1) {
-        *why = "row too large: at most 65536 bytes for rows of 16-byte multiples "
-               "(32768 for 8-byte, 16384 for 4-byte multiples)";
+        *why = "row too large: at most 81920 bytes";
         return 0;
     }
     return ch;
@@ -620,7 +791,7 @@ int inplace_merge_rows(void *data, int64_t L_A, int64_t L_B, int64_t row_bytes, 
     const int ch = rows_chunk(data, row_bytes, key_dtype, &why);
     if (ch == 0) return fail(IM_ERR_INVALID_ARG, why);
     return run_pipeline(key_dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
-                        nullptr, stream, -1, kSplitCorank, kRotLS, RowsArg{row_bytes, ch});
+                        nullptr, stream, -1, kSplitCorank, kRotSwapRev, RowsArg{row_bytes, ch});
 }
 
 size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int key_dtype) {
@@ -631,7 +802,7 @@ size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int k
     size_t need = 0;
     for (int ch : {4, 8, 16}) {
         if (row_bytes % ch != 0 || rows_tile(row_bytes, ch) < 1) continue;
-        Plan pl;
+        Plan pl = {};
         if (!make_plan_rows(ds, key_dtype, row_bytes, ch, std::max<int64_t>(rows, 1), &pl))
             return 0;
         need = std::max(need, carve(pl, 0, nullptr, nullptr));
@@ -639,8 +810,9 @@ size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int k
     return need;
 }
 
-int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n, int64_t total_elems,
-                          int64_t max_instance, int dtype, hipStream_t stream) {
+int batched_inplace_merge_sized(void *data, const int64_t *d_offsets, int64_t n,
+                                int64_t total_elems, int64_t max_instance, int dtype,
+                                hipStream_t stream) {
     if (!valid_dtype(dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
     if (n < 0 || total_elems < 0 || max_instance < 0)
         return fail(IM_ERR_INVALID_ARG, "negative count");
@@ -651,9 +823,9 @@ int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n, int64
                         nullptr, stream);
 }
 
-int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
-                             int64_t total_elems, int64_t max_instance, int key_dtype,
-                             int val_dtype, hipStream_t stream) {
+int batched_inplace_merge_kv_sized(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
+                                   int64_t total_elems, int64_t max_instance, int key_dtype,
+                                   int val_dtype, hipStream_t stream) {
     if (!valid_dtype(key_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
     if (!valid_dtype(val_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported payload dtype");
     if (n < 0 || total_elems < 0 || max_instance < 0)
@@ -666,43 +838,72 @@ int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, i
                         max_instance, 0, 0, nullptr, stream);
 }
 
+// The offsets-only forms read the total d_offsets[2n] back to size the
+// workspace (one 8-byte copy on the stream, then a synchronisation).
+static int read_total(const int64_t *d_offsets, int64_t n, hipStream_t stream, int64_t *total) {
+    if (stream_capturing(stream))
+        return fail(IM_ERR_INVALID_ARG, "the stream is capturing a graph: use the _sized form "
+                                        "through batched_inplace_merge_graph");
+    int64_t v = 0;
+    IM_HIP(hipMemcpyAsync(&v, d_offsets + 2 * n, sizeof(v), hipMemcpyDeviceToHost, stream),
+           "read the offsets' total");
+    IM_HIP(hipStreamSynchronize(stream), "read the offsets' total");
+    if (v < 0 || v > (int64_t(1) << 46)) return fail(IM_ERR_INVALID_ARG, "offsets' total out of range");
+    *total = v;
+    return IM_OK;
+}
+
+int batched_inplace_merge(void *data, const int64_t *d_offsets, int64_t n, int dtype,
+                          hipStream_t stream) {
+    if (!valid_dtype(dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (n < 0) return fail(IM_ERR_INVALID_ARG, "negative count");
+    if (n == 0) { g_err.clear(); return IM_OK; }
+    if (data == nullptr || d_offsets == nullptr) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (n >= (int64_t(1) << 31)) return fail(IM_ERR_INVALID_ARG, "too many instances");
+    int64_t total = 0;
+    int rc = read_total(d_offsets, n, stream, &total);
+    if (rc) return rc;
+    return batched_inplace_merge_sized(data, d_offsets, n, total, 0, dtype, stream);
+}
+
+int batched_inplace_merge_kv(void *keys, void *vals, const int64_t *d_offsets, int64_t n,
+                             int key_dtype, int val_dtype, hipStream_t stream) {
+    if (!valid_dtype(key_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
+    if (!valid_dtype(val_dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported payload dtype");
+    if (n < 0) return fail(IM_ERR_INVALID_ARG, "negative count");
+    if (n == 0) { g_err.clear(); return IM_OK; }
+    if (keys == nullptr || vals == nullptr || d_offsets == nullptr)
+        return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (n >= (int64_t(1) << 31)) return fail(IM_ERR_INVALID_ARG, "too many instances");
+    int64_t total = 0;
+    int rc = read_total(d_offsets, n, stream, &total);
+    if (rc) return rc;
+    return batched_inplace_merge_kv_sized(keys, vals, d_offsets, n, total, 0, key_dtype,
+                                          val_dtype, stream);
+}
+
 int inplace_merge_sort(void *data, int64_t n, int dtype, hipStream_t stream) {
     if (!valid_dtype(dtype)) return fail(IM_ERR_UNSUPPORTED_DTYPE, "unsupported key dtype");
     if (n < 0) return fail(IM_ERR_INVALID_ARG, "negative length");
     if (n <= 1) { g_err.clear(); return IM_OK; }
     if (data == nullptr) return fail(IM_ERR_INVALID_ARG, "null data pointer");
-    DevState *ds = dev_state(nullptr);
-    if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    if (n > (int64_t(1) << 46)) return fail(IM_ERR_INVALID_ARG, "length too large");
+    if (stream_capturing(stream))
+        return fail(IM_ERR_INVALID_ARG, "the stream is capturing a graph");
     const int64_t tile = sort_tile_elems(key_size(dtype));
-    const int64_t max_inst_cnt = (n + 2 * tile - 1) / (2 * tile);
-    {
-        std::lock_guard<std::mutex> lock(ds->mu);
-        if (ds->sort_off_cap < 2 * max_inst_cnt + 1) {
-            if (ds->sort_off) {
-                if (hipDeviceSynchronize() != hipSuccess) return fail(IM_ERR_HIP, "sync");
-                (void)hipFree(ds->sort_off);
-                ds->sort_off = nullptr;
-            }
-            if (hipMalloc(&ds->sort_off, sizeof(int64_t) * (2 * max_inst_cnt + 1)) != hipSuccess) {
-                ds->sort_off = nullptr;
-                ds->sort_off_cap = 0;
-                return fail(IM_ERR_WORKSPACE, "sort offsets allocation failed");
-            }
-            ds->sort_off_cap = 2 * max_inst_cnt + 1;
-        }
-    }
     IM_HIP(launch_tilesort(dtype, data, n, stream), "launch tile sort");
+    // each pass writes its offsets into the shared workspace, after the
+    // workspace's earlier users on other streams (inside run_pipeline)
     for (int64_t w = tile; w < n; w *= 2) {
-        int64_t ni = (n + 2 * w - 1) / (2 * w);
-        IM_HIP(launch_pass_offsets(n, w, ds->sort_off, ni, stream), "launch pass offsets");
-        int rc = run_pipeline(dtype, 0, data, nullptr, ds->sort_off, ni, n, std::min(n, 2 * w), 0, 0,
-                              nullptr, stream);
+        const int64_t ni = (n + 2 * w - 1) / (2 * w);
+        int rc = run_pipeline(dtype, 0, data, nullptr, nullptr, ni, n, std::min(n, 2 * w), 0, 0,
+                              nullptr, stream, -1, kSplitCorank, kRotSwapRev, RowsArg{0, 0}, w);
         if (rc) return rc;
     }
     return IM_OK;
 }
 
-size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dtype) {
+size_t inplace_merge_workspace_bytes_batched(int64_t total_elems, int64_t n_inst, int dtype) {
     if (!valid_dtype(dtype) || total_elems < 0 || n_inst < 0) return 0;
     DevState *ds = dev_state(nullptr);
     if (!ds) return 0;
@@ -711,7 +912,7 @@ size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dt
     size_t need = 0;
     for (int cfg = 0; cfg < kLeafCfgs; ++cfg) {
         for (int ev : {0, 4, 8}) {
-            Plan pl;
+            Plan pl = {};
             if (!make_plan(ds, key_size(dtype), ev, std::max<int64_t>(n_inst, 1),
                            std::max<int64_t>(total_elems, 1), 0, cfg, &pl))
                 return 0;
@@ -719,6 +920,17 @@ size_t inplace_merge_workspace_bytes(int64_t total_elems, int64_t n_inst, int dt
         }
     }
     return need;
+}
+
+size_t inplace_merge_workspace_bytes(int64_t N, int dtype) {
+    if (!valid_dtype(dtype) || N < 0) return 0;
+    // one pair, or the first (widest in instances) pass of a sort of N
+    size_t need = inplace_merge_workspace_bytes_batched(N, 1, dtype);
+    const int64_t tile = sort_tile_elems(key_size(dtype));
+    const int64_t ni = std::max<int64_t>((N + 2 * tile - 1) / (2 * tile), 1);
+    const size_t sort = inplace_merge_workspace_bytes_batched(N, ni, dtype);
+    if (need == 0 || sort == 0) return 0;
+    return std::max(need, sort) + align_up(sizeof(int64_t) * (2 * ni + 1));
 }
 
 int inplace_merge_set_workspace(void *d_ws, size_t bytes) {
@@ -755,6 +967,21 @@ int inplace_merge_fetch_stats(im_stats *out, hipStream_t stream) {
     out->fused_nodes = (int64_t)c.fused;
     if (c.error) return fail(IM_ERR_DEVICE, "device error bits " + std::to_string(c.error));
     return IM_OK;
+}
+
+int inplace_merge_last_stats(merge_stats *out) {
+    return inplace_merge_fetch_stats(out, g_last_stream);
+}
+
+int inplace_merge_device_status(void) {
+    DevState *ds = dev_state(nullptr);
+    if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
+    if (!ds->h_err) return IM_OK;
+    const unsigned bits = __atomic_exchange_n(ds->h_err, 0u, __ATOMIC_ACQ_REL);
+    if (bits == 0) return IM_OK;
+    return fail(IM_ERR_DEVICE, "an enqueued merge raised device error bit " + std::to_string(bits) +
+                                   " (1: a node too large at the last level, 2: a bounded wait "
+                                   "gave up, 4: a descriptor array overflowed)");
 }
 
 int inplace_merge_profile(int enable) {
@@ -812,13 +1039,13 @@ int inplace_merge_variant(void *data, int64_t L_A, int64_t L_B, int dtype, int s
     if (rc) return rc;
     if (split_method != IM_SPLIT_CORANK && split_method != IM_SPLIT_FINDMEDIAN)
         return fail(IM_ERR_INVALID_ARG, "unknown split method");
-    if (rot_method != IM_ROTATE_LS && rot_method != IM_ROTATE_CS)
+    if (rot_method != IM_ROTATE_SWAP_REV && rot_method != IM_ROTATE_CS)
         return fail(IM_ERR_INVALID_ARG, "unknown exchange method");
     if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
     return run_pipeline(dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
                         nullptr, stream, -1,
                         split_method == IM_SPLIT_FINDMEDIAN ? kSplitFindMedian : kSplitCorank,
-                        rot_method == IM_ROTATE_CS ? kRotCS : kRotLS);
+                        rot_method == IM_ROTATE_CS ? kRotCS : kRotSwapRev);
 }
 
 int im_divide(const void *data, int64_t L_A, int64_t L_B, int dtype, int method, int depth,
@@ -867,6 +1094,27 @@ int im_rotate_cs(void *data, int64_t lx, int64_t ly, int elem_bytes, hipStream_t
     hipError_t e = launch_rotate_cs_single(data, lx, ly, elem_bytes, stash, stream);
     hipError_t ef = hipFreeAsync(stash, stream);
     if (e != hipSuccess) return hip_fail(e, "launch circular shifting");
+    if (ef != hipSuccess) return hip_fail(ef, "stash free");
+    return IM_OK;
+}
+
+int im_rotate_ls(void *data, int64_t lx, int64_t ly, int elem_bytes, int64_t *d_swaps,
+                 hipStream_t stream) {
+    if (lx < 0 || ly < 0) return fail(IM_ERR_INVALID_ARG, "negative length");
+    if (elem_bytes != 4 && elem_bytes != 8) return fail(IM_ERR_UNSUPPORTED_DTYPE, "element size");
+    if (lx > (int64_t(1) << 46) || ly > (int64_t(1) << 46))
+        return fail(IM_ERR_INVALID_ARG, "length too large");
+    if (d_swaps) IM_HIP(hipMemsetAsync(d_swaps, 0, sizeof(int64_t), stream), "clear swap count");
+    if (lx == 0 || ly == 0) return IM_OK;
+    if (!data) return fail(IM_ERR_INVALID_ARG, "null data pointer");
+    const int64_t ns = ls_stash_elems(lx, ly);
+    void *stash = nullptr;
+    if (ns > 0)
+        IM_HIP(hipMallocAsync(&stash, (size_t)elem_bytes * ns, stream), "stash allocation");
+    hipError_t e = launch_rotate_ls_single(data, lx, ly, elem_bytes, stash,
+                                           (unsigned long long *)d_swaps, stream);
+    hipError_t ef = stash ? hipFreeAsync(stash, stream) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "launch linear shifting");
     if (ef != hipSuccess) return hip_fail(ef, "stash free");
     return IM_OK;
 }
@@ -929,12 +1177,16 @@ int batched_inplace_merge_graph(im_graph **out, void *data, const int64_t *d_off
     DevState *ds = dev_state(nullptr);
     if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
     const int ek = key_size(dtype);
-    Plan pl;
+    Plan pl = {};
     {
         std::lock_guard<std::mutex> lock(ds->mu);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        load_tune_cache(ds, dev);
         const int cfg = choose_cfg(ds, ek, 0, n, total_elems, -1);
         if (!make_plan(ds, ek, 0, n, total_elems, max_instance, cfg, &pl))
             return fail(IM_ERR_HIP, "could not size the leaf merge grid");
+        ensure_err_word(ds);
     }
     if (pl.leaf_shift == 0)
         return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");
@@ -951,6 +1203,7 @@ int batched_inplace_merge_graph(im_graph **out, void *data, const int64_t *d_off
     }
     Work w;
     carve(pl, 0, g->ws, &w);
+    w.host_err = ds->d_err;
     int th, ipt, depth;
     size_t lds;
     leaf_geometry(ek, 0, pl.cfg, &th, &ipt, &depth, &lds);
@@ -1138,6 +1391,15 @@ int inplace_merge_autotune(const void *data, const int64_t *d_offsets, int64_t n
     {
         std::lock_guard<std::mutex> lock(ds->mu);
         ds->tuned[key_index(ek)][val_index(ev)][size_class(n, total_elems)] = best;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        save_tune_entry(dev, ek, ev, size_class(n, total_elems), best);
+    }
+    if (log_level() >= 2) {
+        std::fprintf(stderr, "[inplace_merge] autotune: class %d, median ms",
+                     size_class(n, total_elems));
+        for (int c = 0; c < kLeafCfgs; ++c) std::fprintf(stderr, " %.4f", med[c]);
+        std::fprintf(stderr, ", chosen %d\n", best);
     }
     if (chosen) *chosen = best;
     g_err.clear();
@@ -1199,7 +1461,20 @@ int merge_model_get_params(const merge_model *m, float *params_out) {
 int merge_model_set_params(merge_model *m, const float *params) {
     if (!m || !params) return fail(IM_ERR_INVALID_ARG, "null pointer");
     std::memcpy(m->host, params, sizeof(m->host));
+    // the error table described the old parameters: searches stay plain
+    // until the model is trained again
+    for (float &v : m->err_b) v = kErrUnknown;
+    m->err_scale = 1.0f;
     return model_upload(m);
+}
+
+int merge_model_adam_step(merge_model *m, const float *d_grad, float *d_m, float *d_v, float lr,
+                          int step, hipStream_t stream) {
+    if (!m || !d_grad || !d_m || !d_v) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (step < 1) return fail(IM_ERR_INVALID_ARG, "Adam steps count from 1");
+    if (!(lr >= 0.0f)) return fail(IM_ERR_INVALID_ARG, "bad learning rate");
+    IM_HIP(launch_mlp_adam(m->d->p, d_grad, d_m, d_v, lr, step, stream), "launch Adam step");
+    return IM_OK;
 }
 
 int merge_model_grad(const merge_model *m, const float *d_x, const float *d_t, int64_t M,
@@ -1224,14 +1499,33 @@ int merge_model_forward(const merge_model *m, const float *d_x, int64_t M, float
     return IM_OK;
 }
 
-int merge_model_train(merge_model *m, const void *data, int64_t L_A, int64_t L_B, int dtype,
+static int train_model(merge_model *m, const void *data, int64_t L_A, int64_t L_B, int dtype,
+                       const merge_train_cfg *cfg, hipStream_t stream);
+
+int merge_model_train(merge_model **pm, const void *data, int64_t L_A, int64_t L_B, int dtype,
                       const merge_train_cfg *cfg, hipStream_t stream) {
-    if (!m || !cfg) return fail(IM_ERR_INVALID_ARG, "null pointer");
+    if (!pm || !cfg) return fail(IM_ERR_INVALID_ARG, "null pointer");
     int rc = check_common(data, L_A, L_B, dtype);
     if (rc) return rc;
     if (L_A == 0 || L_B == 0) return fail(IM_ERR_INVALID_ARG, "both runs must be non-empty");
+    if (cfg->samples < 2 || cfg->steps < 0 || !(cfg->lr > 0.0f))
+        return fail(IM_ERR_INVALID_ARG, "bad config");
+    const bool created = *pm == nullptr;
+    if (created) {
+        rc = merge_model_create(pm, nullptr, cfg->seed);
+        if (rc) return rc;
+    }
+    rc = train_model(*pm, data, L_A, L_B, dtype, cfg, stream);
+    if (rc && created) {
+        merge_model_free(*pm);
+        *pm = nullptr;
+    }
+    return rc;
+}
+
+static int train_model(merge_model *m, const void *data, int64_t L_A, int64_t L_B, int dtype,
+                       const merge_train_cfg *cfg, hipStream_t stream) {
     const int64_t M = cfg->samples;
-    if (M < 2 || cfg->steps < 0 || !(cfg->lr > 0.0f)) return fail(IM_ERR_INVALID_ARG, "bad config");
     const int nb = mlp_grad_blocks(M);
     int64_t *d_k = nullptr, *d_i = nullptr;
     float *d_x = nullptr, *d_t = nullptr, *d_g = nullptr, *d_part = nullptr;
@@ -1258,10 +1552,13 @@ int merge_model_train(merge_model *m, const void *data, int64_t L_A, int64_t L_B
     if (e == hipSuccess) e = launch_mlp_targets(d_i, M, L_A, d_t, stream);
     if (e == hipSuccess) e = hipMemsetAsync(m->d_m, 0, sizeof(float) * kMlpParams, stream);
     if (e == hipSuccess) e = hipMemsetAsync(m->d_v, 0, sizeof(float) * kMlpParams, stream);
+    // cosine decay of the learning rate to zero over the steps
     for (int st = 1; st <= cfg->steps && e == hipSuccess; ++st) {
+        const float lr = (float)((double)cfg->lr * 0.5 *
+                                 (1.0 + std::cos(M_PI * (double)st / (double)cfg->steps)));
         e = launch_mlp_grad(m->d->p, d_x, d_t, M, d_part, nb, stream);
         if (e == hipSuccess) e = launch_mlp_reduce(d_part, nb, d_g, nullptr, stream);
-        if (e == hipSuccess) e = launch_mlp_adam(m->d->p, d_g, m->d_m, m->d_v, cfg->lr, st, stream);
+        if (e == hipSuccess) e = launch_mlp_adam(m->d->p, d_g, m->d_m, m->d_v, lr, st, stream);
     }
     if (e == hipSuccess) e = launch_mlp_errscale(m->d->p, d_k, d_i, M, L_A, L_B, m->d, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1271,6 +1568,7 @@ int merge_model_train(merge_model *m, const void *data, int64_t L_A, int64_t L_B
     if (e != hipSuccess) return hip_fail(e, "training");
     std::memcpy(m->host, h.p, sizeof(m->host));
     m->err_scale = h.err_scale;
+    std::memcpy(m->err_b, h.err_b, sizeof(m->err_b));
     return IM_OK;
 }
 
@@ -1305,11 +1603,13 @@ int merge_model_save(const merge_model *m, const char *path) {
     if (rc) return rc;
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(IM_ERR_INVALID_ARG, std::string("cannot open ") + path);
-    const char magic[8] = {'I', 'M', 'M', 'L', 'P', '1', 0, 0};
-    int32_t hdr[2] = {kMlpHidden, kMlpParams};
+    // IMMLP2: parameters, mean error, the bracket table
+    const char magic[8] = {'I', 'M', 'M', 'L', 'P', '2', 0, 0};
+    int32_t hdr[3] = {kMlpHidden, kMlpParams, kErrBuckets};
     bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
               std::fwrite(p, sizeof(p), 1, f) == 1 &&
-              std::fwrite(&m->err_scale, sizeof(float), 1, f) == 1;
+              std::fwrite(&m->err_scale, sizeof(float), 1, f) == 1 &&
+              std::fwrite(m->err_b, sizeof(m->err_b), 1, f) == 1;
     ok = (std::fclose(f) == 0) && ok;
     if (!ok) return fail(IM_ERR_INVALID_ARG, "write failed");
     return IM_OK;
@@ -1320,18 +1620,21 @@ int merge_model_load(merge_model **out, const char *path) {
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(IM_ERR_INVALID_ARG, std::string("cannot open ") + path);
     char magic[8];
-    int32_t hdr[2];
+    int32_t hdr[3];
     float p[kMlpParams];
     float es = 1.0f;
-    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "IMMLP1", 6) == 0 &&
+    float eb[kErrBuckets];
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "IMMLP2", 6) == 0 &&
               std::fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == kMlpHidden &&
-              hdr[1] == kMlpParams && std::fread(p, sizeof(p), 1, f) == 1 &&
-              std::fread(&es, sizeof(float), 1, f) == 1;
+              hdr[1] == kMlpParams && hdr[2] == kErrBuckets &&
+              std::fread(p, sizeof(p), 1, f) == 1 && std::fread(&es, sizeof(float), 1, f) == 1 &&
+              std::fread(eb, sizeof(eb), 1, f) == 1;
     std::fclose(f);
     if (!ok) return fail(IM_ERR_INVALID_ARG, "not a model file of this shape");
     int rc = merge_model_create(out, p, 0);
     if (rc) return rc;
     (*out)->err_scale = es;
+    std::memcpy((*out)->err_b, eb, sizeof(eb));
     return model_upload(*out);
 }
 

@@ -101,10 +101,16 @@ constexpr unsigned kErrCapacity = 4u;       // a descriptor array overflowed
 constexpr unsigned kErrNotSorted = 8u;      // checked mode: a run is unsorted
 constexpr unsigned kErrOffsets = 16u;       // checked mode: offsets not monotone
 
-// The learned split model as the kernels see it (device memory).
+// The learned split model as the kernels see it (device memory).  The
+// prediction error is kept per bucket of the normalised diagonal x = k/N
+// (kErrBuckets equal buckets): err_b[b] is the half-width, in A elements, of
+// the bracket a search starts from when x falls in bucket b.
+constexpr int kErrBuckets = 128;
+constexpr float kErrUnknown = 1e30f;    // no bracket: searches stay plain
 struct MlpDev {
-    float p[kMlpParams];   // w1[H], b1[H], w2[H], b2
-    float err_scale;       // typical |prediction error| in A elements (>= 1)
+    float p[kMlpParams];      // w1[H], b1[H], w2[H], b2
+    float err_scale;          // mean |prediction error| in A elements (>= 1)
+    float err_b[kErrBuckets];
     float pad[2];
 };
 
@@ -121,7 +127,7 @@ struct Plan {
     uint32_t epoch;         // value a tile writes to its "inputs read" flag
     int32_t cfg;            // leaf-merge configuration (tile size per workgroup)
     int32_t split_method;   // kSplitCorank or kSplitFindMedian
-    int32_t rot_method;     // kRotLS or kRotCS
+    int32_t rot_method;     // kRotSwapRev or kRotCS
     int64_t cap_stash;      // circular shifting: stash slots per level
     int32_t fuse;           // fuse two division levels into one exchange where possible
     int32_t leaf_shift;     // bits of the tile count in the packed leaf/tile counter
@@ -131,15 +137,19 @@ struct Plan {
     // exchange units per element (1: exchanges move whole elements).
     int64_t row_stride;
     int64_t rot_scale;
+    // Merge-sort pass: width of the sorted runs it pairs (0: not a sort
+    // pass).  The pass's offsets are then written into the workspace.
+    int64_t sort_width;
 };
 
 // Split of a division node: the exact co-rank (symmetric or middle diagonal),
 // or FindMedian (Sec. 3.3, Alg. 1) guarded by a validity and balance check.
 constexpr int kSplitCorank = 0;
 constexpr int kSplitFindMedian = 1;
-// Partition exchange: linear shifting (block swap / three reversals) or
-// circular shifting (cycles of Sec. 3.4).
-constexpr int kRotLS = 0;
+// Partition exchange of the merge: a block swap (one linear-shifting step)
+// when the parts are equal, else three reversals; or circular shifting
+// (cycles of Sec. 3.4).
+constexpr int kRotSwapRev = 0;
 constexpr int kRotCS = 1;
 constexpr int kCsSeg = 256;      // cycle steps per lane in circular shifting
 constexpr int kCsLanes = 256;    // lanes per circular-shifting work item
@@ -160,7 +170,21 @@ struct Work {
     int64_t *offsets1;       // [3] offsets of a single-instance call
     void *cs_stash_k;        // circular shifting: first value of each cycle segment
     void *cs_stash_v;        // ... and its payload
+    int64_t *sort_off;       // merge-sort pass: the pass's instance offsets (else null)
+    unsigned int *host_err;  // device view of a host-memory word that receives the
+                             // error bits as they are raised (may be null)
 };
+
+// Raise a device-side error bit: in the call's counters (read under IM_CHECK
+// and by the statistics call) and in the host-memory word that the library
+// reads without a synchronisation.  The host word takes a plain store at
+// system scope (no read-modify-write over the host link): concurrent raisers
+// may overwrite each other's bit, but the word stays nonzero.
+__device__ __forceinline__ void raise_error(const Work &w, unsigned bit) {
+    atomicOr(&w.ctr->error, bit);
+    if (w.host_err)
+        __hip_atomic_store(w.host_err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // Key-type dispatch codes (match im_dtype of the public header).
 enum KeyCode { kI32 = 0, kU32 = 1, kI64 = 2, kU64 = 3 };
@@ -184,6 +208,10 @@ hipError_t launch_fill32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, int *depth,
                    size_t *lds_bytes);
 int leaf_grid(int esize_k, int esize_v, int cfg);   // persistent grid (resident workgroups)
+// One-launch merge of a single small pair (configuration 0 tiles; the grid is
+// one workgroup per tile, at most a quarter of the resident workgroups).
+hipError_t launch_smallmerge(int key, int esize_v, void *keys, void *vals, int64_t la, int64_t lb,
+                             const Plan &pl, const Work &w, hipStream_t s);
 const void *leaf_kernel_ptr(int key, int esize_v, int cfg);
 
 hipError_t launch_corank(int key, const void *data, int64_t la, int64_t lb, const int64_t *d_k,
@@ -195,6 +223,12 @@ hipError_t launch_rotate_single(void *data, int64_t lx, int64_t ly, int esize, h
 int64_t cs_lanes(int64_t lx, int64_t ly);
 hipError_t launch_rotate_cs_single(void *data, int64_t lx, int64_t ly, int esize, void *stash,
                                    hipStream_t s);
+// Linear shifting step by step (stand-alone): the stash holds
+// ls_stash_elems(lx, ly) elements; d_swaps (may be null) accumulates the
+// element swaps performed.
+int64_t ls_stash_elems(int64_t lx, int64_t ly);
+hipError_t launch_rotate_ls_single(void *data, int64_t lx, int64_t ly, int esize, void *stash,
+                                   unsigned long long *d_swaps, hipStream_t s);
 // Recursive division into 2^depth pairs without moving data (im_split.hip).
 hipError_t launch_divide(int key, const void *data, int64_t la, int64_t lb, int method,
                          int level, const int64_t *nodes_in, int64_t *nodes_out, hipStream_t s);

@@ -206,7 +206,7 @@ __device__ __forceinline__ bool wait_window(const TileGeo &g, const Plan &pl, co
         }
     }
     bad = __syncthreads_or(bad);
-    if (bad && threadIdx.x == 0) atomicOr(&w.ctr->error, kErrBarrierSpin);
+    if (bad && threadIdx.x == 0) raise_error(w, kErrBarrierSpin);
     return !bad;
 }
 
@@ -474,12 +474,140 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
     }
 }
 
+// ---- one-launch merge of a small pair ---------------------------------------
+// A single pair of at most a quarter of the resident tiles is merged by ONE
+// launch of plain (non-cooperative) workgroups, one tile each, with no
+// division and no planning launches.  Each workgroup finds what the planning
+// kernels would give it straight from the keys, six binary searches side by
+// side in the lanes of its first wave: the co-ranks of its window's two ends,
+// and the tiles that read its window -- the output tiles of the window's
+// first and last A elements (A[x] lands at x + #{B < A[x]}) and of its first
+// and last B elements (B[y] lands at y + #{A <= B[y]}).  Then, as a leaf
+// tile: stage in LDS and publish "inputs read", merge, wait for the readers'
+// flags, store.  Every workgroup publishes before it waits, so the waits end
+// once every workgroup of the grid has started.  The grid is at most a
+// quarter of what the device holds at once: with the stream's earlier work
+// finished, its workgroups are dispatched together even beside up to three
+// other such launches; a wait that gives up raises the error bit and skips
+// its store.  Workgroup 0 resets the counters (no other workgroup writes
+// them, except the error bit of a wait that gave up, which takes seconds).
+template <typename K>
+__device__ __forceinline__ int64_t count_below(const K *__restrict__ X, int64_t n, K v) {
+    int64_t lo = 0, hi = n;          // first index with X[m] >= v
+    while (lo < hi) {
+        const int64_t m = lo + ((hi - lo) >> 1);
+        if (X[m] < v) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+template <typename K>
+__device__ __forceinline__ int64_t count_at_most(const K *__restrict__ X, int64_t n, K v) {
+    int64_t lo = 0, hi = n;          // first index with X[m] > v
+    while (lo < hi) {
+        const int64_t m = lo + ((hi - lo) >> 1);
+        if (X[m] <= v) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+template <typename K, typename V, int THREADS, int IPT>
+__global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys, V *__restrict__ vals,
+                                                           int64_t la, int64_t lb, Plan pl, Work w) {
+    using Ops = LeafOps<K, V, THREADS, IPT>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t s_geo[6];
+    K *sk = reinterpret_cast<K *>(smem);
+    V *sv = reinterpret_cast<V *>(smem + (size_t)Ops::PE * sizeof(K));
+    const int64_t S = la + lb, T = Ops::T;
+    const int64_t ntiles = (S + T - 1) / T;
+    const int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int64_t d0 = t * T, d1 = d0 + T < S ? d0 + T : S;
+    const K *A = keys, *B = keys + la;
+    if (t == 0) {
+        constexpr int64_t kWords = (int64_t)(sizeof(Counters) / sizeof(unsigned long long));
+        for (int64_t q = threadIdx.x; q < kWords; q += THREADS)
+            reinterpret_cast<unsigned long long *>(w.ctr)[q] = 0ull;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            w.ctr->level_nodes[0] = 1;
+            w.ctr->levels_used = 1;
+            w.ctr->leaves = 1;
+            w.ctr->tiles = (unsigned long long)ntiles;
+            w.ctr->leaf_elems = (unsigned long long)S;
+        }
+    }
+    if (threadIdx.x < 6) {
+        const int q = threadIdx.x;
+        int64_t r = -1;
+        if (q < 2) {
+            // co-rank of diagonal d0 (q = 0) or d1 (q = 1)
+            const int64_t d = q == 0 ? d0 : d1;
+            int64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+            while (lo < hi) {
+                const int64_t m = lo + ((hi - lo) >> 1);
+                if (A[m] <= B[d - 1 - m]) lo = m + 1;
+                else hi = m;
+            }
+            r = lo;
+        } else if (q < 4) {
+            // output tile of the window's first / last A element
+            const int64_t x0 = d0, x1 = d1 < la ? d1 : la;
+            if (x0 < x1) {
+                const int64_t x = q == 2 ? x0 : x1 - 1;
+                r = (x + count_below(B, lb, A[x])) / T;
+            }
+        } else {
+            // output tile of the window's first / last B element
+            const int64_t y0 = (d0 > la ? d0 : la) - la, y1 = d1 - la;
+            if (y0 < y1) {
+                const int64_t y = q == 4 ? y0 : y1 - 1;
+                r = (y + count_at_most(A, la, B[y])) / T;
+            }
+        }
+        s_geo[q] = r;
+    }
+    __syncthreads();
+    const int64_t ia0 = uniform64(s_geo[0]), ia1 = uniform64(s_geo[1]);
+    TileGeo g;
+    const int n = (int)(d1 - d0);
+    int64_t na64 = ia1 - ia0;    // clamped as in tile_geo (only unsorted input needs it)
+    const int64_t na_lo = (d1 - lb - ia0) > 0 ? (d1 - lb - ia0) : 0;
+    const int64_t na_hi = (la - ia0) < (int64_t)n ? (la - ia0) : (int64_t)n;
+    if (na64 < na_lo) na64 = na_lo;
+    if (na64 > na_hi) na64 = na_hi;
+    g.out0 = d0;
+    g.n = n;
+    g.na = (int)na64;
+    g.a0 = ia0;
+    g.b0 = la + (d0 - ia0);
+    g.tbase = 0;
+    g.ntiles = (int32_t)ntiles;
+    g.local = (int32_t)t;
+    const int64_t a_lo = uniform64(s_geo[2]), a_hi = uniform64(s_geo[3]);
+    const int64_t b_lo = uniform64(s_geo[4]), b_hi = uniform64(s_geo[5]);
+    g.alo = a_lo >= 0 ? (int32_t)a_lo : 0;
+    g.ahi = a_lo >= 0 ? (int32_t)a_hi : -1;
+    g.blo = b_lo >= 0 ? (int32_t)b_lo : 0;
+    g.bhi = b_lo >= 0 ? (int32_t)b_hi : -1;
+    Ops::stage(keys, vals, g, sk, sv, pl, w);
+    K out[IPT];
+    V vout[Ops::VN];
+    Ops::template merge<false>(g, sk, sv, out, vout);
+    if (Ops::wait_readers(g, pl, w)) Ops::store(keys, vals, g, out, vout);
+}
+
 // ---- wide rows --------------------------------------------------------------
 // Leaf merge of rows of W bytes ordered by their leading key: the elements of
 // the paper's experiments (Sec. 4), a key followed by a payload.  Rows move
 // in chunks of CH = 16, 8 or 4 bytes (the largest that divides W); a thread
-// holds kRowChunks chunks of a tile, so a tile is R output rows with
-// R * W <= 512 * kRowChunks * CH (64, 32 or 16 KiB).  Per tile:
+// holds row_chunks(CH) chunks of a tile (8, 16 or 40), so a tile is R
+// output rows with R * W <= 512 * row_chunks(CH) * CH (64, 64 or 80 KiB:
+// the paper's largest element, a key and 16384 ints = 65540 bytes, moves
+// in 4-byte chunks, one row per tile).  Per tile:
 //   1. the keys of its A- and B-slices go to LDS (one load per row);
 //   2. each thread merges four consecutive outputs (stable, ties take A) and
 //      records each output row's input row in LDS;
@@ -493,7 +621,9 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
 // which it reads before it waits: the depth-2 argument above applies, so a
 // leaf may have 2G tiles.
 constexpr int kRowThreads = 512;
-constexpr int kRowChunks = 8;                              // per thread and tile
+// chunks per thread and tile, by chunk bytes: two register sets of 32, 32
+// or 40 words
+__host__ __device__ constexpr int row_chunks(int ch) { return ch == 16 ? 8 : (ch == 8 ? 16 : 40); }
 constexpr int kRowMaxRows = 2048;
 constexpr int kRowOutsPerThread = kRowMaxRows / kRowThreads;
 
@@ -522,7 +652,7 @@ struct RowGeo {
 template <typename K, int CH>
 struct RowOps {
     typedef typename ChunkT<CH>::type C;
-    static constexpr int CPT = kRowChunks;
+    static constexpr int CPT = row_chunks(CH);
 
     static __device__ __forceinline__ int64_t row_of(const TileGeo &g, int x) {
         return x < g.na ? g.a0 + x : g.b0 + (x - g.na);
@@ -662,7 +792,7 @@ static const void *rows_kernel(int key, int ch) {
 }
 
 int rows_tile(int64_t row_bytes, int ch) {
-    int64_t r = (int64_t)kRowThreads * kRowChunks * ch / row_bytes;
+    int64_t r = (int64_t)kRowThreads * row_chunks(ch) * ch / row_bytes;
     if (r > kRowMaxRows) r = kRowMaxRows;
     return r < 1 ? 0 : (int)r;
 }
@@ -947,6 +1077,34 @@ const void *leaf_kernel_ptr(int key, int esize_v, int cfg) {
     IM_LEAF_CASES(X)
 #undef X
     return nullptr;
+}
+
+static const void *small_kernel_ptr(int key, int esize_v) {
+#define X(K, V, C, TH, IPT, DEPTH)                                               \
+    if constexpr (C == 0) {                                                      \
+        if (KeyOf<K>::code == key && ValSize<V>::v == esize_v)                   \
+            return (const void *)&k_smallmerge<K, V, TH, IPT>;                   \
+    }
+    IM_LEAF_CASES(X)
+#undef X
+    return nullptr;
+}
+
+hipError_t launch_smallmerge(int key, int esize_v, void *keys, void *vals, int64_t la, int64_t lb,
+                             const Plan &pl, const Work &w, hipStream_t s) {
+    int th, ipt, depth;
+    size_t lds;
+    const int esize_k = (key == kI32 || key == kU32) ? 4 : 8;
+    leaf_geometry(esize_k, esize_v, 0, &th, &ipt, &depth, &lds);
+    const void *fn = small_kernel_ptr(key, esize_v);
+    if (!fn || pl.tile != (int64_t)th * ipt) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int64_t ntiles = (la + lb + pl.tile - 1) / pl.tile;
+    Plan plc = pl;
+    Work wc = w;
+    void *args[] = {&keys, &vals, &la, &lb, &plc, &wc};
+    return hipLaunchKernel(fn, dim3((unsigned)ntiles), dim3(th), args, (unsigned)lds, s);
 }
 
 int leaf_grid(int esize_k, int esize_v, int cfg) {

@@ -122,21 +122,32 @@ __global__ void k_mlp_targets(const int64_t *__restrict__ is, int64_t m, int64_t
         ts[p] = la > 0 ? (float)((double)is[p] / (double)la) : 0.0f;
 }
 
-// Mean |prediction - label| in A elements over the training diagonals; it
-// sets the first step of the correcting exponential search.
+// Prediction errors in A elements over the training diagonals: their mean
+// (err_scale, a statistic) and, per bucket of x, the bracket half-width that
+// the searches start from: 1.25 x the largest error seen in the bucket or
+// its two neighbours, plus 32 elements (fp32 resolution of x and y at
+// 2^29 elements).  A bucket with no sample takes the largest error overall.
+// The brackets are estimates between samples; the searches check both ends.
 __global__ __launch_bounds__(1024) void k_mlp_errscale(const float *__restrict__ prm, const int64_t *__restrict__ ks,
                                const int64_t *__restrict__ is, int64_t m, int64_t la, int64_t lb,
                                MlpDev *__restrict__ model) {
     __shared__ MlpDev sm;
     __shared__ double red[1024];
+    __shared__ int bmax[kErrBuckets];     // float bits of non-negative errors (-1: none)
     for (int j = threadIdx.x; j < kMlpParams; j += blockDim.x) sm.p[j] = prm[j];
+    for (int j = threadIdx.x; j < kErrBuckets; j += blockDim.x) bmax[j] = -1;
     __syncthreads();
     const int64_t n = la + lb;
     double acc = 0.0;
     for (int64_t p = threadIdx.x; p < m; p += blockDim.x) {
-        float x = n > 0 ? (float)((double)ks[p] / (double)n) : 0.0f;
-        double pred = (double)mlp_eval(&sm, x) * (double)la;
-        acc += fabs(pred - (double)is[p]);
+        const float x = n > 0 ? (float)((double)ks[p] / (double)n) : 0.0f;
+        const double pred = (double)mlp_eval(&sm, x) * (double)la;
+        double err = fabs(pred - (double)is[p]);
+        if (!(err == err) || err > 1e30) err = 1e30;
+        acc += err;
+        int b = (int)(x * (float)kErrBuckets);
+        b = b < 0 ? 0 : (b >= kErrBuckets ? kErrBuckets - 1 : b);
+        atomicMax(&bmax[b], __float_as_int((float)err));
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -144,7 +155,22 @@ __global__ __launch_bounds__(1024) void k_mlp_errscale(const float *__restrict__
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
+    // largest error over all buckets (for buckets without samples)
+    __shared__ int gmax;
+    if (threadIdx.x == 0) gmax = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < kErrBuckets; j += blockDim.x)
+        if (bmax[j] >= 0) atomicMax(&gmax, bmax[j]);
+    __syncthreads();
     for (int j = threadIdx.x; j < kMlpParams; j += blockDim.x) model->p[j] = prm[j];
+    for (int j = threadIdx.x; j < kErrBuckets; j += blockDim.x) {
+        int v = -1;
+        for (int q = j - 1; q <= j + 1; ++q)
+            if (q >= 0 && q < kErrBuckets && bmax[q] > v) v = bmax[q];
+        const float worst = __int_as_float(v >= 0 ? v : gmax);
+        const float hw = 1.25f * worst + 32.0f;
+        model->err_b[j] = hw < kErrUnknown ? hw : kErrUnknown;
+    }
     if (threadIdx.x == 0) {
         double mean = m > 0 ? red[0] / (double)m : 1.0;
         if (!(mean >= 1.0)) mean = 1.0;

@@ -442,6 +442,144 @@ hipError_t launch_rotate_cs_single(void *data, int64_t lx, int64_t ly, int esize
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Linear shifting step by step (Sec. 3.4): the stand-alone exchange that
+// performs the paper's swaps.  X|Y with |X| != |Y|: the smaller block is
+// swapped, element pair by element pair, with the block at the far end of
+// the larger one, which puts it in its final place; the rest is the same
+// problem on what remains.  A run of q such steps with the same smaller
+// block size s (one quotient of Euclid's algorithm on the two lengths) keeps
+// one block F fixed and swaps it with B_1, B_2, ..., B_q in turn:
+//   |X| <= |Y|: F = X at the front, B_t = the t-th block of s from the end;
+//   |X| >  |Y|: F = Y's place (right after X), B_t = the t-th block of s
+//               from the front.
+// Column j of a run is a chain: F[j] <-> B_1[j], then F[j] <-> B_2[j], ...
+// Columns are independent, so one lane per (column, segment of kLsSeg
+// chain positions) performs those swaps in order; the value held at F[j]
+// between two swaps stays in the lane's register, so F[j] is written once
+// per run.  A lane's segment starts from the value the chain carries into
+// it: F[j] for the first segment, else the old value at the last position of
+// the segment before, which phase 0 copies to a stash before phase 1 walks.
+// Every run is one launch (two with a stash); runs are in Euclid's order.
+// Lanes count the swaps they perform: Sigma q*s = L_A + L_B - gcd.
+constexpr int kLsSeg = 256;
+constexpr int kLsThreads = 256;
+constexpr int kLsBatch = 8;
+
+struct LsRun {
+    int64_t f;       // first element of the fixed block
+    int64_t b1;      // first element of B_1
+    int64_t bstep;   // B_t = b1 + (t - 1) * bstep  (+s or -s)
+    int64_t s, q;    // block size, swaps per column
+    int64_t nseg;    // segments per column (ceil(q / kLsSeg))
+};
+
+template <typename E>
+__global__ __launch_bounds__(kLsThreads) void k_ls_run(E *__restrict__ p, LsRun r, int phase,
+                                                      E *__restrict__ stash,
+                                                      unsigned long long *__restrict__ swaps) {
+    const int64_t lanes = r.s * r.nseg;
+    unsigned long long done = 0;
+    for (int64_t lane = (int64_t)blockIdx.x * kLsThreads + threadIdx.x; lane < lanes;
+         lane += (int64_t)gridDim.x * kLsThreads) {
+        const int64_t j = lane % r.s, k = lane / r.s;
+        const int64_t t0 = k * kLsSeg + 1;
+        const int64_t t1 = (k + 1) * kLsSeg < r.q ? (k + 1) * kLsSeg : r.q;
+        if (phase == 0) {
+            stash[lane] = k == 0 ? p[r.f + j] : p[r.b1 + (t0 - 2) * r.bstep + j];
+            continue;
+        }
+        E carry = r.nseg == 1 ? p[r.f + j] : stash[lane];
+        for (int64_t t = t0; t <= t1; t += kLsBatch) {
+            E v[kLsBatch];
+#pragma unroll
+            for (int b = 0; b < kLsBatch; ++b)
+                if (t + b <= t1) v[b] = p[r.b1 + (t + b - 1) * r.bstep + j];
+#pragma unroll
+            for (int b = 0; b < kLsBatch; ++b) {
+                if (t + b <= t1) {
+                    p[r.b1 + (t + b - 1) * r.bstep + j] = carry;
+                    carry = v[b];
+                }
+            }
+        }
+        done += (unsigned long long)(t1 - t0 + 1);
+        if (k == r.nseg - 1) p[r.f + j] = carry;
+    }
+    if (phase == 0 || swaps == nullptr) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) done += __shfl_xor(done, o, 64);
+    if ((threadIdx.x & 63) == 0 && done) atomicAdd(swaps, done);
+}
+
+// The runs of linear shifting on X|Y, in order (host side).
+static void ls_runs(int64_t lx, int64_t ly, void (*emit)(const LsRun &, void *), void *ctx) {
+    int64_t base = 0;
+    while (lx > 0 && ly > 0) {
+        LsRun r;
+        if (lx <= ly) {
+            r.s = lx;
+            r.q = ly / lx;
+            r.f = base;
+            r.b1 = base + lx + ly - lx;
+            r.bstep = -lx;
+            ly -= r.q * lx;
+        } else {
+            r.s = ly;
+            r.q = lx / ly;
+            r.f = base + lx;
+            r.b1 = base;
+            r.bstep = ly;
+            base += r.q * ly;
+            lx -= r.q * ly;
+        }
+        r.nseg = (r.q + kLsSeg - 1) / kLsSeg;
+        emit(r, ctx);
+    }
+}
+
+int64_t ls_stash_elems(int64_t lx, int64_t ly) {
+    int64_t need = 0;
+    ls_runs(lx, ly, [](const LsRun &r, void *c) {
+        int64_t *n = (int64_t *)c;
+        if (r.nseg > 1 && r.s * r.nseg > *n) *n = r.s * r.nseg;
+    }, &need);
+    return need;
+}
+
+struct LsLaunch {
+    void *data, *stash;
+    unsigned long long *swaps;
+    int esize;
+    hipStream_t s;
+    hipError_t err;
+};
+
+template <typename E>
+static void ls_launch_run(const LsRun &r, LsLaunch *L) {
+    const int64_t lanes = r.s * r.nseg;
+    const int64_t g64 = (lanes + kLsThreads - 1) / kLsThreads;
+    const int g = (int)(g64 < 8192 ? g64 : 8192);
+    for (int ph = r.nseg > 1 ? 0 : 1; ph < 2 && L->err == hipSuccess; ++ph) {
+        hipLaunchKernelGGL(k_ls_run<E>, dim3(g), dim3(kLsThreads), 0, L->s, (E *)L->data, r, ph,
+                           (E *)L->stash, L->swaps);
+        L->err = hipGetLastError();
+    }
+}
+
+hipError_t launch_rotate_ls_single(void *data, int64_t lx, int64_t ly, int esize, void *stash,
+                                   unsigned long long *d_swaps, hipStream_t s) {
+    if (esize != 4 && esize != 8) return hipErrorInvalidValue;
+    LsLaunch L{data, stash, d_swaps, esize, s, hipSuccess};
+    ls_runs(lx, ly, [](const LsRun &r, void *c) {
+        LsLaunch *l = (LsLaunch *)c;
+        if (l->err != hipSuccess) return;
+        if (l->esize == 4) ls_launch_run<uint32_t>(r, l);
+        else ls_launch_run<uint64_t>(r, l);
+    }, &L);
+    return L.err;
+}
+
 template <typename EK, typename EV>
 static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, int level,
                         int phase, hipStream_t s) {

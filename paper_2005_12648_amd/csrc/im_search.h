@@ -47,42 +47,46 @@ __device__ __forceinline__ int64_t corank_plain(KP A, int64_t la, KP B, int64_t 
     return corank_binary(A, la, B, lb, k, lo, hi, probes);
 }
 
-// FindMedian (Sec. 3.3, Alg. 1): a double binary search for a pivot pair
-// (p_A, p_B) with A[0,p_A) <= B[p_B,..) and B[0,p_B) <= A[p_A,..) that keeps
-// |A0|+|B0| close to |A1|+|B1|, in O(log L_A + log L_B) probes.  The probes
-// start at the middles of A and B; when the loop stops because the probed
-// values are equal, that probe pair is the result (the printed listing tests
-// p_A, p_B before setting them and recomputes midpoints after such a stop).
-// One lane, sequential dependent probes.  `probes` counts value pairs read.
+// FindMedian (Sec. 3.3, Alg. 1): a pivot pair (pa, pb) with
+// A[0,pa) <= B[pb,..) and B[0,pb) <= A[pa,..) that keeps the lower halves'
+// size close to the upper halves', in O(log la + log lb) dependent looks.
+// Each index bisects a window of its run and sits at the window's middle.
+// A look at the two values decides which window shrinks: while the lower
+// halves hold fewer elements than the upper ones the index on the smaller
+// value moves up, otherwise the index on the larger value moves down (equal
+// values rank A's as the larger).  The search ends on an empty window (both
+// indexes then take their window's middle) or on a look at two equal values,
+// which is a valid pivot by itself (the printed listing recomputes middles
+// there, which breaks the pivot property when keys repeat).  One lane;
+// `probes` counts the looks (value pairs read).
 template <typename KP>
 __device__ __forceinline__ void find_median(KP A, int64_t la, KP B, int64_t lb, int64_t &pa,
                                             int64_t &pb, uint32_t &probes) {
-    if (la == 0 || lb == 0 || A[la - 1] <= B[0]) { pa = la; pb = 0; return; }
-    if (!(A[0] <= B[lb - 1])) { pa = 0; pb = lb; return; }
-    int64_t left_a = 0, limit_a = la, left_b = 0, limit_b = lb;
-    pa = la / 2;
-    pb = lb / 2;
-    auto va = A[pa], vb = B[pb];
-    ++probes;
-    while (left_a < limit_a && left_b < limit_b && va != vb) {
-        pa = (limit_a - left_a) / 2 + left_a;
-        pb = (limit_b - left_b) / 2 + left_b;
-        va = A[pa];
-        vb = B[pb];
+    if (la == 0 || lb == 0 || A[la - 1] <= B[0]) { pa = la; pb = 0; return; }   // in order
+    if (!(A[0] <= B[lb - 1])) { pa = 0; pb = lb; return; }                    // reversed
+    int64_t alo = 0, ahi = la, blo = 0, bhi = lb;
+    for (bool first = true;; first = false) {
+        pa = alo + ((ahi - alo) >> 1);
+        pb = blo + ((bhi - blo) >> 1);
+        const auto va = A[pa];
+        const auto vb = B[pb];
         ++probes;
-        const int64_t lo = pa + pb, hi = (la - pa) + (lb - pb);
-        if (va < vb) {
-            if (lo < hi) left_a = pa + 1;
-            else limit_b = pb;
+        const bool same = va == vb;
+        if (first && same) return;
+        const bool up = 2 * (pa + pb) < la + lb;     // lower halves the smaller
+        const bool move_a = up == (va < vb);
+        if (move_a) {
+            if (up) alo = pa + 1;
+            else ahi = pa;
         } else {
-            if (lo < hi) left_b = pb + 1;
-            else limit_a = pa;
+            if (up) blo = pb + 1;
+            else bhi = pb;
         }
-        // the loop test reads the values at the current probe pair
+        if (alo >= ahi || blo >= bhi) break;
+        if (same) return;
     }
-    if (left_a < limit_a && left_b < limit_b) return;   // stopped on an equal probe
-    pa = (limit_a - left_a) / 2 + left_a;
-    pb = (limit_b - left_b) / 2 + left_b;
+    pa = alo + ((ahi - alo) >> 1);
+    pb = blo + ((bhi - blo) >> 1);
 }
 
 // fp32 forward pass of the 1 -> H -> 1 ReLU network.
@@ -96,9 +100,35 @@ __device__ __forceinline__ float mlp_eval(const MlpDev *__restrict__ M, float x)
     return y;
 }
 
+// Half-width of the search bracket around a prediction at x = k/N.
+__device__ __forceinline__ float mlp_halfwidth(const MlpDev *__restrict__ M, float x) {
+    int b = (int)(x * (float)kErrBuckets);
+    b = b < 0 ? 0 : (b >= kErrBuckets ? kErrBuckets - 1 : b);
+    return M->err_b[b];
+}
+
+// Predicted local co-rank g of the searched sub-problem and its bracket
+// half-width e (both in A elements of the sub-problem; g not clamped).
+// False when the prediction is unusable (NaN) or its bracket would not be
+// narrower than `frac` of the range [lo, hi]: the search then stays plain.
+__device__ __forceinline__ bool mlp_bracket(const MlpDev *__restrict__ M, int64_t kg,
+                                            int64_t n_inst, int64_t la_inst, int64_t i0,
+                                            int64_t lo, int64_t hi, int frac, double &g,
+                                            double &e) {
+    const float x = n_inst > 0 ? (float)((double)kg / (double)n_inst) : 0.0f;
+    g = (double)mlp_eval(M, x) * (double)la_inst - (double)i0;
+    e = (double)mlp_halfwidth(M, x);
+    if (!(g == g) || !(e >= 0.0)) return false;
+    return (2.0 * e + 1.0) * (double)frac < (double)(hi - lo);
+}
+
 // Learned co-rank.  kg: global diagonal of the instance (size n_inst, A size
 // la_inst); i0: global co-rank of the start of the searched sub-problem
-// (A/B here are that sub-problem's parts), k: local diagonal.
+// (A/B here are that sub-problem's parts), k: local diagonal.  The bracket
+// [L, R] around the prediction holds the answer when P(L-1) holds and P(R)
+// does not; both ends are probed together, then a binary search runs inside.
+// A bracket end that fails gallops outward from it (doubling steps).  When
+// the bracket is not 4x narrower than the range, plain binary search.
 template <typename KP>
 __device__ __forceinline__ int64_t corank_learned(KP A, int64_t la, KP B, int64_t lb, int64_t k,
                                                   const MlpDev *__restrict__ M, int64_t kg,
@@ -106,38 +136,47 @@ __device__ __forceinline__ int64_t corank_learned(KP A, int64_t la, KP B, int64_
                                                   uint32_t &probes) {
     int64_t lo = k > lb ? k - lb : 0;
     int64_t hi = k < la ? k : la;
-    if (hi - lo <= 1) return corank_binary(A, la, B, lb, k, lo, hi, probes);
-    float x = n_inst > 0 ? (float)((double)kg / (double)n_inst) : 0.0f;
-    float y = mlp_eval(M, x);
-    double gd = (double)y * (double)la_inst - (double)i0;
-    int64_t g;
-    if (!(gd == gd)) g = lo;                     // NaN prediction: start at lo
-    else if (gd <= (double)lo) g = lo;
-    else if (gd >= (double)hi) g = hi;
-    else g = (int64_t)llrint(gd);
-    int64_t step = (int64_t)M->err_scale;
-    if (step < 1) step = 1;
-    int64_t blo, bhi;
-    if (g < hi && (++probes, A[g] <= B[k - 1 - g])) {
-        // answer > g: gallop to the right
-        blo = g + 1;
+    double gd, e;
+    if (hi - lo <= 1 || !mlp_bracket(M, kg, n_inst, la_inst, i0, lo, hi, 4, gd, e))
+        return corank_binary(A, la, B, lb, k, lo, hi, probes);
+    const double fl = floor(gd - e), fr = ceil(gd + e);
+    const int64_t L = fl <= (double)lo ? lo : (fl >= (double)hi ? hi : (int64_t)fl);
+    const int64_t R = fr <= (double)lo ? lo : (fr >= (double)hi ? hi : (int64_t)fr);
+    // both ends in one round of loads
+    const bool needL = L > lo, needR = R < hi;
+    bool pl = true, pr = false;
+    if (needL) {
+        ++probes;
+        pl = A[L - 1] <= B[k - L];
+    }
+    if (needR) {
+        ++probes;
+        pr = A[R] <= B[k - 1 - R];
+    }
+    int64_t blo = L, bhi = R;
+    int64_t step = (int64_t)e + 1;
+    if (!pl) {
+        // the answer is below L: gallop down from L - 1
+        bhi = L - 1;
+        blo = lo;
         for (;;) {
-            int64_t m = g + step;
-            if (m >= hi) { bhi = hi; break; }
-            ++probes;
-            if (!(A[m] <= B[k - 1 - m])) { bhi = m; break; }
-            blo = m + 1;
-            step <<= 1;
-        }
-    } else {
-        // answer <= g: gallop to the left
-        bhi = g;
-        for (;;) {
-            int64_t m = g - step;
-            if (m < lo) { blo = lo; break; }
+            const int64_t m = bhi - step;
+            if (m < lo) break;
             ++probes;
             if (A[m] <= B[k - 1 - m]) { blo = m + 1; break; }
             bhi = m;
+            step <<= 1;
+        }
+    } else if (pr) {
+        // the answer is above R: gallop up from R + 1
+        blo = R + 1;
+        bhi = hi;
+        for (;;) {
+            const int64_t m = blo + step - 1;
+            if (m >= hi) break;
+            ++probes;
+            if (!(A[m] <= B[k - 1 - m])) { bhi = m; break; }
+            blo = m + 1;
             step <<= 1;
         }
     }
@@ -193,9 +232,11 @@ __device__ __forceinline__ int64_t corank_group(KP A, int64_t la, KP B, int64_t 
     return group_search<W>(lo, hi, [&](int64_t m) { return A[m] <= B[k - 1 - m]; }, rounds);
 }
 
-// Learned group co-rank: the first round probes W points spaced by the
-// model's typical error around its prediction, then the plain rounds go on
-// inside the bracket that round leaves (always exact).
+// Learned group co-rank: the first round probes W points spread evenly over
+// the bracket around the prediction (its half-width from the model's error
+// table), then the plain rounds go on inside the bracket that round leaves
+// (always exact: an answer outside the bracket leaves [lo, first point] or
+// [last point, hi]).  A bracket not 8x narrower than the range: plain rounds.
 template <int W, typename KP>
 __device__ __forceinline__ int64_t corank_group_learned(KP A, int64_t la, KP B, int64_t lb,
                                                         int64_t k, const MlpDev *__restrict__ M,
@@ -208,17 +249,14 @@ __device__ __forceinline__ int64_t corank_group_learned(KP A, int64_t la, KP B, 
     const uint64_t gmask = W == 64 ? ~0ull : ((1ull << W) - 1);
     int64_t lo = k > lb ? k - lb : 0;
     int64_t hi = k < la ? k : la;
-    const bool wide = hi - lo > W;
+    double gd = 0.0, e = 0.0;
+    // the same on every lane of the group (same arguments)
+    const bool use = hi - lo > W && mlp_bracket(M, kg, n_inst, la_inst, i0, lo, hi, 8, gd, e);
     bool p = false;
     int64_t m = lo;
-    if (wide) {
-        const float x = n_inst > 0 ? (float)((double)kg / (double)n_inst) : 0.0f;
-        const double gd = (double)mlp_eval(M, x) * (double)la_inst - (double)i0;
-        int64_t g;
-        if (!(gd == gd) || gd <= (double)lo) g = lo;
-        else if (gd >= (double)hi) g = hi;
-        else g = (int64_t)llrint(gd);
-        int64_t step = (int64_t)M->err_scale;
+    if (use) {
+        const int64_t g = gd <= (double)lo ? lo : (gd >= (double)hi ? hi : (int64_t)llrint(gd));
+        int64_t step = (int64_t)ceil((2.0 * e + 1.0) / (double)(W - 1));
         if (step < 1) step = 1;
         // probe g + (gl - W/2) * step, clamped into [lo, hi-1]: non-decreasing in gl
         m = g + (int64_t)(gl - W / 2) * step;
@@ -230,7 +268,7 @@ __device__ __forceinline__ int64_t corank_group_learned(KP A, int64_t la, KP B, 
     // every lane takes part in the shuffles; sources lie in the same group
     const int64_t m_prev = __shfl(m, gbase + (c > 0 ? c - 1 : 0), 64);
     const int64_t m_next = __shfl(m, gbase + (c < W ? c : W - 1), 64);
-    if (wide) {
+    if (use) {
         ++rounds;
         const int64_t nlo = c > 0 ? m_prev + 1 : lo;
         const int64_t nhi = c < W ? m_next : hi;

@@ -98,7 +98,7 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
             const unsigned long long st =
                 atomicAdd(&w.ctr->level_stash[level], (unsigned long long)(g * nseg));
             if ((int64_t)st + g * nseg > pl.cap_stash) {
-                atomicOr(&w.ctr->error, kErrCapacity);
+                raise_error(w, kErrCapacity);
                 return;
             }
             stash0 = (int64_t)st;
@@ -114,7 +114,7 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
                                           (1ull << kRotCountShift) | (unsigned long long)nw);
     unsigned long long slot = packed >> kRotCountShift;
     if ((int64_t)slot >= pl.cap_rot) {
-        atomicOr(&w.ctr->error, kErrCapacity);
+        raise_error(w, kErrCapacity);
         return;
     }
     Rot r;
@@ -152,10 +152,10 @@ __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const N
     // Only those leaves are counted in tiles and leaf_elems: the tile kernels
     // never meet a tile of a dropped leaf.
     if ((int64_t)slot >= pl.cap_leaves) {
-        atomicOr(&w.ctr->error, kErrCapacity);
+        raise_error(w, kErrCapacity);
         return;
     }
-    if ((int64_t)(tstart + nt) > pl.cap_tiles) atomicOr(&w.ctr->error, kErrCapacity);
+    if ((int64_t)(tstart + nt) > pl.cap_tiles) raise_error(w, kErrCapacity);
     atomicAdd(&w.ctr->tiles, nt);
     atomicAdd(&w.ctr->leaf_elems, (unsigned long long)S);
     Leaf lf;
@@ -179,7 +179,7 @@ __device__ __forceinline__ void emit_split(const Plan &pl, const Work &w, int le
     if (la - i > 0 && j > 0) emit_rot(pl, w, level, nd.base + i, la - i, j);
     unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level + 1], 2ull);
     if ((int64_t)slot + 1 >= pl.cap_nodes) {
-        atomicOr(&w.ctr->error, kErrCapacity);
+        raise_error(w, kErrCapacity);
         return;
     }
     Node l, r;
@@ -293,8 +293,9 @@ __device__ __forceinline__ bool fz_closure(const FusedPerm &f, int64_t S, int64_
 
 // Cycles of equal-length pieces between the cuts, one lane per piece;
 // written as exchange descriptors (slots and work items reserved at once, in
-// lane order).  False (nothing emitted) if an image is not a piece of the
-// same length or a cycle is longer than kMaxCyc.
+// lane order).  False (nothing moved) if an image is not a piece of the
+// same length, a cycle is longer than kMaxCyc, or the descriptor array is
+// full (an error bit is then raised).
 __device__ __forceinline__ bool fz_emit_cycles(const Plan &pl, const Work &w, int level,
                                                int64_t base, const FusedPerm &f, int64_t c,
                                                int nc) {
@@ -341,8 +342,18 @@ __device__ __forceinline__ bool fz_emit_cycles(const Plan &pl, const Work &w, in
     packed = __shfl(packed, 0, 64);
     const int64_t slot0 = (int64_t)(packed >> kRotCountShift);
     if (slot0 + ncyc > pl.cap_rot) {
-        if (lane == 0) atomicOr(&w.ctr->error, kErrCapacity);
-        return true;
+        // The reservation cannot be undone: the slots of it that lie inside
+        // the array get empty exchanges (no stale descriptor is ever read),
+        // and the node falls back to its plain split.
+        if (lane == 0) raise_error(w, kErrCapacity);
+        if (leader && slot0 + sc - 1 < pl.cap_rot) {
+            Rot r = {};
+            r.w0 = (int64_t)(packed & kRotWorkMask) + sw - nw;
+            r.nw = nw;
+            r.stash0 = -1;
+            w.rot[slot0 + sc - 1] = r;
+        }
+        return false;
     }
     if (leader) {
         Rot r;
@@ -376,7 +387,7 @@ __device__ __forceinline__ void emit_node(const Plan &pl, const Work &w, int lev
                                           const Node &nd) {
     unsigned long long slot = atomicAdd(&w.ctr->level_nodes[level], 1ull);
     if ((int64_t)slot >= pl.cap_nodes) {
-        atomicOr(&w.ctr->error, kErrCapacity);
+        raise_error(w, kErrCapacity);
         return;
     }
     out[slot] = nd;
@@ -457,7 +468,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
             } else if (la + lb <= pl.leaf_cap || (la < lb ? la : lb) <= pl.leaf_span) {
                 emit_leaf(pl, w, nd);
             } else if (level + 1 >= pl.max_levels) {
-                atomicOr(&w.ctr->error, kErrOversizeLeaf);   // depth bound violated
+                raise_error(w, kErrOversizeLeaf);   // depth bound violated
             } else {
                 const int64_t S = la + lb;
                 const int64_t mx = la > lb ? la : lb;

@@ -19,3 +19,19 @@ def dev():
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     return torch.device("cuda:0")
+
+
+@pytest.fixture(autouse=True)
+def _device_error_bits(request):
+    """After every GPU test: no kernel may have raised a device-side error bit
+    (read from the library's host word without a synchronisation, after the
+    device has been synchronised here)."""
+    yield
+    if request.node.get_closest_marker("gpu") is None:
+        return
+    import torch
+    if not torch.cuda.is_available():
+        return
+    import paper_2005_12648_amd as im
+    torch.cuda.synchronize()
+    im.device_status()

@@ -78,7 +78,7 @@ def test_c5_plain_and_learned_full(dev):
     say("full-size c5", data.size)
     want = oracle.merge(data, la)
     t = torch.from_numpy(data).to(dev)
-    model = im.MergeModel(seed=5).train(t, la, samples=8192, steps=1500)
+    model = im.MergeModel(seed=5).train(t, la, samples=8192, steps=20000, lr=1e-2)
     im.inplace_merge(t, la)
     torch.cuda.synchronize()
     assert int(np.count_nonzero(t.cpu().numpy() != want)) == 0

@@ -5,9 +5,16 @@ and exactness of the corrected co-ranks.
   (fp32 on the device: rtol 1e-4 / atol 1e-6 for gradients, 1e-5 for outputs);
 * co-ranks found from a prediction equal the oracle's for every diagonal,
   whatever the parameters (trained, untrained, NaN);
+* one Adam step of the device kernel against oracle.MLP64.adam_step from the
+  same state (fp32 tolerance), several steps in a row, and a short training
+  run against the oracle's own gradient + Adam trajectory on the same
+  training diagonals and learning-rate schedule;
 * merges through the learned path equal the oracle bit for bit;
-* the trained network needs fewer probes per diagonal than plain binary
-  search on the mixture workload (what the network buys).
+* what the network buys, measured on the merge's own searches: the probes
+  per split search of a learned merge (node searches and tile co-ranks, as
+  counted by the device) are fewer than those of the plain merge of the
+  same input, with and without forced division levels; and on a dense set
+  of global diagonals.
 Trained weights themselves are not compared ("parity unpinned").
 """
 import math
@@ -66,12 +73,115 @@ def test_gradient_parity(dev, M):
     assert math.isclose(float(loss.item()), lref, rel_tol=1e-4, abs_tol=1e-7)
 
 
+def _cosine_lr(lr, s, steps):
+    # the training schedule of merge_model_train, rounded to fp32 as passed
+    return float(np.float32(lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))))
+
+
+def test_adam_step_matches_oracle(dev):
+    th = random_params(11)
+    m = im.MergeModel(params=th)
+    r = np.random.default_rng(12)
+    mo = torch.zeros(im.MLP_PARAMS, dtype=torch.float32, device=dev)
+    ve = torch.zeros(im.MLP_PARAMS, dtype=torch.float32, device=dev)
+    for step in range(1, 8):
+        # gradients of every scale, some exactly zero
+        g = (r.normal(0, 1, im.MLP_PARAMS) * 10.0 ** r.integers(-6, 2, im.MLP_PARAMS))
+        g[r.integers(0, im.MLP_PARAMS, 5)] = 0.0
+        g = g.astype(np.float32)
+        lr = 1e-2 / step
+        th0 = m.params().numpy().astype(np.float64)
+        m0, v0 = mo.cpu().numpy().astype(np.float64), ve.cpu().numpy().astype(np.float64)
+        m.adam_step(d(g, dev), mo, ve, lr, step)
+        torch.cuda.synchronize()
+        want_th, want_m, want_v = oracle.MLP64.adam_step(th0, g.astype(np.float64), m0, v0, step,
+                                                         lr=float(np.float32(lr)))
+        got_th = m.params().numpy().astype(np.float64)
+        # fp32 tolerance, relative to the magnitudes of the terms summed (a
+        # moment can cancel): the kernel's constants 1 - 0.9f and 1 - 0.999f
+        # are 2.4e-7 and 1.3e-5 off in relative terms, each fp32 operation
+        # adds 6e-8 (the bias corrections cancel most of the second constant's
+        # error in the update)
+        g64 = g.astype(np.float64)
+        m_terms = 0.9 * np.abs(m0) + 0.1 * np.abs(g64)
+        v_terms = 0.999 * v0 + 0.001 * g64 * g64
+        assert np.all(np.abs(mo.cpu().numpy() - want_m) <= 1e-6 * m_terms + 1e-38), step
+        assert np.all(np.abs(ve.cpu().numpy() - want_v) <= 3e-5 * v_terms + 1e-38), step
+        # the update itself; the parameter's own rounding adds at most half
+        # an ulp of the parameter
+        du_got, du_want = got_th - th0, want_th - th0
+        c1, c2 = 1.0 - 0.9 ** step, 1.0 - 0.999 ** step
+        scale = float(np.float32(lr)) * (m_terms / c1) / (np.sqrt(want_v / c2) + 1e-8)
+        tol = 3e-5 * scale + np.spacing(np.abs(th0).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(du_got - du_want) <= tol), step
+
+
+def test_training_trajectory_matches_oracle(dev):
+    # a short run of merge_model_train (grad, reduce, Adam kernels with the
+    # cosine schedule) against the oracle doing the same steps in fp64 from
+    # the same initial parameters on the same training diagonals
+    data, la = gen.make("c5", scale=12)           # 2^16 + 2^16
+    n = data.size
+    M, steps, lr = 512, 6, 2e-3
+    model = im.MergeModel(seed=21)
+    th = model.params().numpy().astype(np.float64)
+    model.train(d(data, dev), la, samples=M, steps=steps, lr=lr)
+    got = model.params().numpy().astype(np.float64)
+    p = np.arange(M, dtype=np.float64)
+    ks = np.minimum(np.floor((p + 0.5) * n / M).astype(np.int64), n)
+    x = (ks / n).astype(np.float32).astype(np.float64)
+    t = (oracle.corank(data[:la], data[la:], ks) / la).astype(np.float32).astype(np.float64)
+    net = oracle.MLP64(32)
+    mo = np.zeros_like(th)
+    ve = np.zeros_like(th)
+    gmin = np.full(th.size, np.inf)
+    gmax = 0.0
+    for s in range(1, steps + 1):
+        g = net.grad(th, x, t)
+        gmin = np.minimum(gmin, np.abs(g))
+        gmax = max(gmax, float(np.abs(g).max()))
+        th, mo, ve = net.adam_step(th, g, mo, ve, s, lr=_cosine_lr(lr, s, steps))
+    # components whose gradient stays well above fp32 noise follow the
+    # oracle closely; an Adam step of a component whose gradient is at the
+    # noise level can take either sign, so those are bounded by the steps
+    firm = gmin > 1e-4 * gmax
+    assert firm.sum() >= 20
+    err = np.abs(got - th)
+    say("trajectory: max err firm %.2e, other %.2e" % (err[firm].max(), err[~firm].max(initial=0)))
+    assert np.all(err[firm] <= 1e-5 + 1e-4 * np.abs(th[firm]))
+    assert np.all(err <= 2 * lr * steps + 1e-5)
+
+
 @pytest.fixture(scope="module")
 def mixture(dev):
     data, la = gen.make("c5", scale=8)          # 2^20 + 2^20 of the mixture workload
     t = d(data, dev)
-    model = im.MergeModel(seed=7).train(t, la, samples=4096, steps=1500, lr=3e-3)
+    model = im.MergeModel(seed=7).train(t, la, samples=8192, steps=20000, lr=1e-2)
     return data, la, t, model
+
+
+@pytest.mark.parametrize("tiles", [None, 24])
+def test_learned_merge_spends_fewer_probes(dev, mixture, monkeypatch, tiles):
+    # the searches the merge itself makes: node splits (cooperative rounds)
+    # and tile co-ranks, as counted on the device, same input both ways
+    data, la, _, model = mixture
+    if tiles:
+        monkeypatch.setenv("IM_LEAF_TILES", str(tiles))
+    want = oracle.merge(data, la)
+    t = d(data, dev)
+    im.inplace_merge(t, la)
+    sp = im.fetch_stats()
+    assert np.array_equal(t.cpu().numpy(), want)
+    t = d(data, dev)
+    model.merge(t, la)
+    sl = im.fetch_stats()
+    assert np.array_equal(t.cpu().numpy(), want)
+    assert sl["searches"] == sp["searches"] and sp["searches"] > 0
+    pp = sp["search_probes"] / sp["searches"]
+    pl = sl["search_probes"] / sl["searches"]
+    say("probes per search in the merge (leaf tiles %s): learned %.2f, plain %.2f, %d searches"
+        % (tiles, pl, pp, sp["searches"]))
+    assert pl < pp
 
 
 def test_learned_corank_exact_and_cheaper(dev, mixture):
@@ -126,7 +236,7 @@ def test_save_load_roundtrip(dev, mixture):
     a, pa = model.corank(t, la, d(ks, dev))
     b, pb = m2.corank(t, la, d(ks, dev))
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
-    assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy())   # same error scale
+    assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy())   # same error table
 
 
 def test_training_reduces_loss(dev, mixture):

@@ -66,7 +66,10 @@ def run(rows, la, dev):
 # (row bytes, rows in A, rows in B): chunk 16 / 8 / 4 bytes, ragged tiles
 SHAPES = [(4, 70001, 65537), (8, 40000, 50003), (12, 30001, 29999), (16, 25000, 27001),
           (20, 20011, 19999), (64, 9001, 12007), (100, 5003, 4001), (256, 3001, 2999),
-          (1000, 1201, 999), (4096, 301, 277), (16384, 77, 91), (65536, 23, 19)]
+          (1000, 1201, 999), (4096, 301, 277), (16384, 77, 91), (65536, 23, 19),
+          # the paper's largest element (key + 16384 ints); 8-byte multiples
+          # above 32 KiB; above 64 KiB in 4-byte chunks
+          (65540, 23, 19), (32776, 40, 33), (81920, 17, 21)]
 
 
 @pytest.mark.parametrize("row_bytes,la,lb", SHAPES)
@@ -79,6 +82,14 @@ def test_rows_shapes(dev, env, row_bytes, la, lb):
     # (with one-row tiles and a two-tile leaf capacity every node ends in an
     # early exit or a whole exchange, and no leaf is left to merge)
     assert st["leaf_elems"] + st["rotated_elems"] > 0
+
+
+def test_rows_too_wide_refused(dev):
+    rows = np.zeros((4, 81924 // 4), dtype=np.int32)
+    t = d(rows, dev)
+    with pytest.raises(im.IMError) as e:
+        im.inplace_merge_rows(t, 2)
+    assert e.value.code == im.ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("dt", [np.int32, np.uint32, np.int64, np.uint64])

@@ -74,7 +74,7 @@ def test_divide_w1_full_depth(dev):
 
 
 @pytest.mark.parametrize("split", [im.SPLIT_CORANK, im.SPLIT_FINDMEDIAN])
-@pytest.mark.parametrize("rot", [im.ROTATE_LS, im.ROTATE_CS])
+@pytest.mark.parametrize("rot", [im.ROTATE_SWAP_REV, im.ROTATE_CS])
 @pytest.mark.parametrize("tiles", [1, 3])
 def test_variant_merges(dev, leaf_tiles, split, rot, tiles):
     leaf_tiles(tiles)
@@ -96,7 +96,7 @@ def test_variant_int_types(dev, leaf_tiles, dt):
     leaf_tiles(2)
     data = gen.pair_uniform(70001, 65432, 12, dtype=dt)
     for split in (im.SPLIT_CORANK, im.SPLIT_FINDMEDIAN):
-        for rot in (im.ROTATE_LS, im.ROTATE_CS):
+        for rot in (im.ROTATE_SWAP_REV, im.ROTATE_CS):
             t = d(data, dev)
             im.inplace_merge_variant(t, 70001, split, rot)
             assert np.array_equal(h(t), oracle.merge(data, 70001)), (split, rot)
@@ -117,6 +117,27 @@ def test_rotate_cs_matches_definition(dev, dt):
         im.rotate_cs(t, lx)
         want = oracle.rotate(x.astype(np.int64), lx).astype(dt)
         assert np.array_equal(h(t), want), (lx, ly)
+
+
+# linear shifting: one long run of 1-element swaps, equal parts (a single
+# block swap), runs of many swaps longer than a segment in both directions,
+# tiny and coprime shapes, chains of exactly one segment
+LS_CASES = CS_CASES + [(7, 300001), (300001, 7), (256, 256 * 257), (256 * 257 + 5, 256),
+                       (1000, 1000 * 600 + 999), (2, 3), (0, 5), (5, 0)]
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.int64])
+def test_rotate_ls_matches_definition_and_counts(dev, dt):
+    for lx, ly in LS_CASES:
+        x = np.arange(lx + ly, dtype=dt) * 3 + 1
+        say("rotate_ls", lx, ly)
+        t = d(x, dev)
+        _, swaps = im.rotate_ls(t, lx)
+        want = oracle.rotate(x.astype(np.int64), lx).astype(dt)
+        assert np.array_equal(h(t), want), (lx, ly)
+        # the paper's swap count, as the oracle's linear shifting performs it
+        _, want_swaps = oracle.rotate_ls(x.astype(np.int64), lx)
+        assert swaps == want_swaps, (lx, ly, swaps, want_swaps)
 
 
 @pytest.mark.parametrize("dt", [np.int32, np.uint32, np.int64, np.uint64])

@@ -58,8 +58,15 @@ def test_validation_codes_without_device_work():
     assert "null" in _err(lib)
     assert lib.inplace_merge_kv(fake, None, 3, 3, 0, 0, None) == -1
     assert lib.inplace_merge_kv(fake, fake, 3, 3, 0, 17, None) == -2
-    assert lib.batched_inplace_merge(fake, None, 5, 100, 0, 0, None) == -1
-    assert lib.batched_inplace_merge(fake, fake, -5, 100, 0, 0, None) == -1
+    assert lib.batched_inplace_merge(fake, None, 5, 0, None) == -1
+    assert lib.batched_inplace_merge(fake, fake, -5, 0, None) == -1
+    assert lib.batched_inplace_merge(fake, fake, 5, 9, None) == -2
+    assert lib.batched_inplace_merge_kv(fake, None, fake, 5, 0, 0, None) == -1
+    assert lib.batched_inplace_merge_sized(fake, None, 5, 100, 0, 0, None) == -1
+    assert lib.batched_inplace_merge_sized(fake, fake, -5, 100, 0, 0, None) == -1
+    assert lib.batched_inplace_merge_kv_sized(fake, fake, fake, 5, 100, 0, 0, 9, None) == -2
+    assert lib.merge_model_train(None, fake, 4, 4, 0, None, None) == -1
+    assert lib.inplace_merge_last_stats(None) == -1
     assert lib.inplace_merge_sort(fake, -3, 0, None) == -1
     assert lib.im_rotate(fake, 3, 4, 3, None) == -2
     assert lib.im_corank(fake, 3, 3, 0, None, 5, None, None, None) == -1
@@ -127,10 +134,55 @@ def test_rows_validation_without_device_work():
     assert lib.inplace_merge_rows(fake, 4, 4, 0, 0, None) == -1             # row bytes
     assert lib.inplace_merge_rows(fake, 4, 4, 6, 0, None) == -1             # not a multiple of 4
     assert lib.inplace_merge_rows(fake, 4, 4, 12, 2, None) == -1            # 8-byte key
-    assert lib.inplace_merge_rows(fake, 4, 4, 65552, 0, None) == -1         # too wide
+    assert lib.inplace_merge_rows(fake, 4, 4, 81924, 0, None) == -1         # too wide
     assert "too large" in _err(lib)
-    assert lib.inplace_merge_rows(fake, 4, 4, 20004, 0, None) == -1         # 4-byte chunks
+    assert lib.inplace_merge_rows(fake, 4, 4, 81928, 0, None) == -1         # 8-byte chunks
     assert lib.inplace_merge_rows(ctypes.c_void_p(0x1002), 4, 4, 64, 0, None) == -1   # alignment
     assert lib.inplace_merge_rows(fake, 0, 9, 64, 0, None) == 0             # nothing to merge
     assert lib.inplace_merge_rows_workspace_bytes(-1, 64, 0) == 0
     assert lib.inplace_merge_rows_workspace_bytes(100, 0, 0) == 0
+
+
+def _declaration(name):
+    """Parameter list of a header declaration, whitespace-normalised."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"([A-Za-z_][A-Za-z0-9_ \*]*?)\b" + name + r"\s*\(([^)]*)\)\s*;", src)
+    assert m, name
+    ret = " ".join(m.group(1).split())
+    args = [" ".join(a.replace("*", " * ").split()) for a in m.group(2).split(",")]
+    # keep the types only (drop the parameter names)
+    types = []
+    for a in args:
+        words = a.split(" ")
+        if words == ["void"]:
+            continue
+        types.append(" ".join(words[:-1]) if len(words) > 1 and words[-1] != "*" else a)
+    return ret, types
+
+
+def test_boundary_matches_the_scope_table():
+    # the calls of the boundary, with the argument types they are specified with
+    want = {
+        "inplace_merge": ("int", ["void *", "int64_t", "int64_t", "int", "hipStream_t"]),
+        "inplace_merge_kv": ("int", ["void *", "void *", "int64_t", "int64_t", "int", "int",
+                                     "hipStream_t"]),
+        "batched_inplace_merge": ("int", ["void *", "const int64_t *", "int64_t", "int",
+                                          "hipStream_t"]),
+        "batched_inplace_merge_kv": ("int", ["void *", "void *", "const int64_t *", "int64_t",
+                                             "int", "int", "hipStream_t"]),
+        "inplace_merge_workspace_bytes": ("size_t", ["int64_t", "int"]),
+        "inplace_merge_set_workspace": ("int", ["void *", "size_t"]),
+        "inplace_merge_last_error": ("const char *", []),
+        "merge_model_train": ("int", ["merge_model * *", "const void *", "int64_t", "int64_t",
+                                      "int", "const merge_train_cfg *", "hipStream_t"]),
+        "inplace_merge_learned": ("int", ["void *", "int64_t", "int64_t", "int",
+                                          "const merge_model *", "hipStream_t"]),
+        "merge_model_save": ("int", ["const merge_model *", "const char *"]),
+        "merge_model_load": ("int", ["merge_model * *", "const char *"]),
+        "merge_model_free": ("int", ["merge_model *"]),
+        "inplace_merge_last_stats": ("int", ["merge_stats *"]),
+    }
+    for name, (ret, types) in want.items():
+        got_ret, got_types = _declaration(name)
+        assert got_ret.endswith(ret), (name, got_ret)
+        assert got_types == types, (name, got_types)
