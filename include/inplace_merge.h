@@ -104,6 +104,25 @@ typedef struct {
  * A[last] <= B[0]; when A[0] > B[last] a single exchange B|A is done. */
 int inplace_merge(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream);
 
+/* inplace_merge() for callers that cannot allocate device memory (code
+ * recorded into a graph by the caller's own means, tight serving loops,
+ * hosts that forbid allocation during operation).  It calls no hipMalloc,
+ * hipFree, pinned-host or event allocation: its workspace is a static
+ * device array of 4 MiB that the library holds on every device it runs on
+ * until the process ends.  The result equals inplace_merge()'s.  A merge
+ * whose workspace (descriptors, counters, tile flags: about 32 bytes per
+ * 17,920 int32 or 8,704 int64 elements, plus a few KiB) does not fit in the
+ * array is refused with IM_ERR_WORKSPACE before any work is enqueued (int32
+ * inputs of a few 10^9 elements fit).  Every call on a device shares that
+ * device's array and leaves its last contents there: two such calls whose
+ * work overlaps in time on one device (different streams, or different host
+ * threads without ordering) race and give wrong results; calls on one
+ * stream are ordered.  It does not share the workspace of the other entry
+ * points, so it may overlap with them.  Device error bits reach the caller
+ * only under IM_CHECK=1 or through inplace_merge_fetch_stats (the host
+ * error word is pinned memory, allocated by the other entry points). */
+int inplace_merge_noalloc(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream);
+
 /* Key + payload variant (structure of arrays): keys[] and vals[] have
  * L_A+L_B elements each; only keys are compared, every move carries the
  * payload.  val_dtype: any im_dtype (only its size, 4 or 8 bytes, matters). */

@@ -96,6 +96,7 @@ def load():
     vp, i64, i32, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
     sig = {
         "inplace_merge": [vp, i64, i64, c_int, vp],
+        "inplace_merge_noalloc": [vp, i64, i64, c_int, vp],
         "inplace_merge_kv": [vp, vp, i64, i64, c_int, c_int, vp],
         "inplace_merge_rows": [vp, i64, i64, i64, c_int, vp],
         "batched_inplace_merge": [vp, vp, i64, c_int, vp],

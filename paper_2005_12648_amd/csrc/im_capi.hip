@@ -111,6 +111,12 @@ struct DevState {
     // calls); the rest of the layout always starts after them.
     int64_t flag_cap = 0;
     uint32_t epoch = 0;
+    // The allocation-free entry point's workspace: this device's copy of the
+    // static `scratch` array (its address, looked up once), with its own
+    // flag bookkeeping.
+    void *scr_ptr = nullptr;
+    int64_t scr_flag_cap = 0;
+    uint32_t scr_epoch = 0;
     std::string cache_path;      // the IM_AUTOTUNE_CACHE file last read for this device
     DevState() {
         for (auto &a : tuned)
@@ -121,6 +127,11 @@ struct DevState {
 
 std::atomic<int> g_force_cfg{-1};   // inplace_merge_set_config
 
+// Workspace of inplace_merge_noalloc: a fixed device array, one copy per
+// device, held until the process ends.  Host code never uses its name as an
+// address: the device address comes from hipGetSymbolAddress (scratch_base).
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 int size_class(int64_t n_inst, int64_t total) {
     int64_t mean = total / std::max<int64_t>(n_inst, 1);
@@ -466,6 +477,20 @@ void ensure_err_word(DevState *ds) {
     ds->d_err = (unsigned *)d;
 }
 
+// This device's address of `scratch` (looked up on the device's first
+// allocation-free call, with the device current and its lock held).
+int scratch_base(DevState *ds, void **out) {
+    if (!ds->scr_ptr) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "address of the static scratch array");
+        if (p == nullptr) return fail(IM_ERR_HIP, "null address of the static scratch array");
+        ds->scr_ptr = p;
+    }
+    *out = ds->scr_ptr;
+    return IM_OK;
+}
+
 bool stream_capturing(hipStream_t s) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
@@ -561,7 +586,8 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
                  int64_t n_inst, int64_t total, int64_t max_inst, int64_t la, int64_t lb,
                  const MlpDev *mlp, hipStream_t s, int cfg_override = -1,
                  int split_method = kSplitCorank, int rot_method = kRotSwapRev,
-                 RowsArg rows = RowsArg{0, 0}, int64_t sort_width = 0) {
+                 RowsArg rows = RowsArg{0, 0}, int64_t sort_width = 0,
+                 bool static_scratch = false) {
     int dev = 0;
     DevState *ds = dev_state(&dev);
     if (!ds) return fail(IM_ERR_HIP, "no current HIP device");
@@ -572,7 +598,7 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         return fail(IM_ERR_INVALID_ARG, "the stream is capturing a graph: record the merge "
                                         "with batched_inplace_merge_graph instead");
     std::lock_guard<std::mutex> lock(ds->mu);
-    ensure_err_word(ds);
+    if (!static_scratch) ensure_err_word(ds);    // (pinned host memory: an allocation)
     load_tune_cache(ds, dev);
     const int ek = key_size(key_dt);
     Plan pl = {};
@@ -590,23 +616,41 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     pl.rot_method = rot_method;
     pl.sort_width = sort_width;
     if (split_method != kSplitCorank || rot_method != kRotSwapRev) pl.fuse = 0;   // the paper's modes as such
-    int64_t &flag_cap = ds->flag_cap;
-    uint32_t &epoch = ds->epoch;
+    int64_t &flag_cap = static_scratch ? ds->scr_flag_cap : ds->flag_cap;
+    uint32_t &epoch = static_scratch ? ds->scr_epoch : ds->epoch;
     size_t need = carve(pl, flag_cap, nullptr, nullptr);
     void *base = nullptr;
-    int rc = acquire_ws(ds, need, &base);
-    if (rc) return rc;
-    if (carve(pl, flag_cap, nullptr, nullptr) > need) {
-        // the buffer was replaced (flag_cap reset): size again
-        need = carve(pl, flag_cap, nullptr, nullptr);
+    int rc = IM_OK;
+    if (static_scratch) {
+        // the flag region only grows, so a plan that fits now fits with it
+        if (carve(pl, pl.cap_tiles, nullptr, nullptr) > kScratchBytes || need > kScratchBytes)
+            return fail(IM_ERR_WORKSPACE, "this merge needs " +
+                                              std::to_string(std::max(need, carve(pl, pl.cap_tiles,
+                                                                                  nullptr, nullptr))) +
+                                              " bytes of workspace; the static scratch holds " +
+                                              std::to_string(kScratchBytes));
+        rc = scratch_base(ds, &base);
+        if (rc) return rc;
+    } else {
         rc = acquire_ws(ds, need, &base);
         if (rc) return rc;
+        if (carve(pl, flag_cap, nullptr, nullptr) > need) {
+            // the buffer was replaced (flag_cap reset): size again
+            need = carve(pl, flag_cap, nullptr, nullptr);
+            rc = acquire_ws(ds, need, &base);
+            if (rc) return rc;
+        }
     }
     Work w;
     carve(pl, flag_cap, base, &w);
     w.host_err = ds->d_err;
-    rc = ws_enter(ds, s);
-    if (rc) return rc;
+    if (!static_scratch) {
+        // the static scratch is private to the allocation-free calls (they
+        // race with each other by contract), so only the shared workspace
+        // is ordered across streams
+        rc = ws_enter(ds, s);
+        if (rc) return rc;
+    }
     if (sort_width > 0) {
         IM_HIP(launch_pass_offsets(total, sort_width, w.sort_off, n_inst, s), "launch pass offsets");
         d_offsets = w.sort_off;
@@ -625,7 +669,7 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     const bool check = checked_mode();
     if (std::getenv("IM_FAULT") && std::strcmp(std::getenv("IM_FAULT"), "launch") == 0)
         return fail(IM_ERR_HIP, "kernel launch failed (injected)");
-    const bool prof = g_prof;
+    const bool prof = g_prof && !static_scratch;    // (events are created lazily)
     // A single small pair: one launch (im_leaf.hip, k_smallmerge) when it has
     // at most a quarter of the resident tiles.  Not in checked mode, for the
     // paper's split and exchange modes, for the learned split (its searches
@@ -652,8 +696,10 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
             IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
         prof_end(e4, kStLeafMerge, 1, s);
     }
-    rc = ws_leave(ds, s);
-    if (rc) return rc;
+    if (!static_scratch) {
+        rc = ws_leave(ds, s);
+        if (rc) return rc;
+    }
 
     record_stats(pl, w);
     g_last_stream = s;
@@ -661,11 +707,12 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         std::fprintf(stderr,
                      "[inplace_merge] dev %d: %lld instance(s), %lld elements, key %d B, payload "
                      "%d B%s; leaf config %d (tile %lld, grid %d), leaf capacity %lld, span %lld, "
-                     "%d level(s) enqueued, fusion %s, workspace %zu B%s\n",
+                     "%d level(s) enqueued, fusion %s, workspace %zu B%s%s\n",
                      dev, (long long)n_inst, (long long)total, ek, ev,
                      rows.bytes > 0 ? " (rows)" : "", pl.cfg, (long long)pl.tile, pl.grid_leaf,
                      (long long)pl.leaf_cap, (long long)pl.leaf_span, pl.max_levels,
-                     pl.fuse ? "on" : "off", need, small ? ", one launch" : "");
+                     pl.fuse ? "on" : "off", need, static_scratch ? " (static scratch)" : "",
+                     small ? ", one launch" : "");
     if (check) {
         unsigned bits = 0;
         rc = read_error_bits(w.ctr, s, &bits);
@@ -741,6 +788,14 @@ int inplace_merge(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t s
     if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
     return run_pipeline(dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
                         nullptr, stream);
+}
+
+int inplace_merge_noalloc(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t stream) {
+    int rc = check_common(data, L_A, L_B, dtype);
+    if (rc) return rc;
+    if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
+    return run_pipeline(dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
+                        nullptr, stream, -1, kSplitCorank, kRotSwapRev, RowsArg{0, 0}, 0, true);
 }
 
 int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B, int key_dtype,
