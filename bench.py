@@ -272,8 +272,19 @@ def bench_variant(torch, im, oracle, gen, dev, name, steps):
     want = oracle.merge(pristine.cpu().numpy(), la)
     bad = mismatches(bufs[0], want)
     n = la + lb
-    return {"workload": "int32 %d+%d keys in [0,%d)" % (la, lb, hi), "gelem_s": round(n / ms / 1e6, 2),
-            "ms": round(ms, 4), "mismatches": bad}
+    out = {"workload": "int32 %d+%d keys in [0,%d)" % (la, lb, hi), "gelem_s": round(n / ms / 1e6, 2),
+           "ms": round(ms, 4), "mismatches": bad}
+    if name == "c1":
+        # the same merges through the division path (one-launch path off)
+        os.environ["IM_SMALL"] = "0"
+        try:
+            ms_d, _, bufs_d = timed_merges(torch, im, pristine, la, 50, 1)
+        finally:
+            del os.environ["IM_SMALL"]
+        out["one_launch_path"] = True
+        out["division_path_ms"] = round(ms_d, 4)
+        out["mismatches_division_path"] = mismatches(bufs_d[0], want)
+    return out
 
 
 def event_timed(torch, pristine, buf, fn, reps):
@@ -618,10 +629,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--forms", choices=["all", "none", "rows", "learned", "exchanges"],
+    ap.add_argument("--forms", choices=["all", "none", "rows", "learned", "exchanges", "c1"],
                     default="all",
                     help="other workloads after the headline: all, none, or only the rows, "
-                         "the learned-split or the exchange forms")
+                         "the learned-split, the exchange or the small (c1) forms")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (profiling runs: default leaf configuration)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -680,6 +691,8 @@ def main():
         forms["f4_wide_rows"] = bench_rows(torch, im, oracle, gen, dev, 3)
     elif args.forms == "learned":
         forms["c5_learned"] = bench_learned(torch, im, oracle, gen, dev, args.steps)
+    elif args.forms == "c1":
+        forms["c1"] = bench_variant(torch, im, oracle, gen, dev, "c1", 3)
     elif args.forms == "exchanges":
         forms["f3_exchange_and_out_of_place"] = bench_exchanges(torch, im, oracle, gen, dev, 3)
     st = head["stats"]

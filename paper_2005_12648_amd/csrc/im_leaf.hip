@@ -40,6 +40,7 @@
 #include <limits>
 #include <type_traits>
 #include "im_common.h"
+#include "im_search.h"
 
 namespace imerge {
 
@@ -478,8 +479,9 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
 // A single pair of at most a quarter of the resident tiles is merged by ONE
 // launch of plain (non-cooperative) workgroups, one tile each, with no
 // division and no planning launches.  Each workgroup finds what the planning
-// kernels would give it straight from the keys, six binary searches side by
-// side in the lanes of its first wave: the co-ranks of its window's two ends,
+// kernels would give it straight from the keys, six searches side by side,
+// one wavefront each with 64 probes per dependent round (im_search.h,
+// group_search): the co-ranks of its window's two ends,
 // and the tiles that read its window -- the output tiles of the window's
 // first and last A elements (A[x] lands at x + #{B < A[x]}) and of its first
 // and last B elements (B[y] lands at y + #{A <= B[y]}).  Then, as a leaf
@@ -491,28 +493,6 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
 // other such launches; a wait that gives up raises the error bit and skips
 // its store.  Workgroup 0 resets the counters (no other workgroup writes
 // them, except the error bit of a wait that gave up, which takes seconds).
-template <typename K>
-__device__ __forceinline__ int64_t count_below(const K *__restrict__ X, int64_t n, K v) {
-    int64_t lo = 0, hi = n;          // first index with X[m] >= v
-    while (lo < hi) {
-        const int64_t m = lo + ((hi - lo) >> 1);
-        if (X[m] < v) lo = m + 1;
-        else hi = m;
-    }
-    return lo;
-}
-
-template <typename K>
-__device__ __forceinline__ int64_t count_at_most(const K *__restrict__ X, int64_t n, K v) {
-    int64_t lo = 0, hi = n;          // first index with X[m] > v
-    while (lo < hi) {
-        const int64_t m = lo + ((hi - lo) >> 1);
-        if (X[m] <= v) lo = m + 1;
-        else hi = m;
-    }
-    return lo;
-}
-
 template <typename K, typename V, int THREADS, int IPT>
 __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys, V *__restrict__ vals,
                                                            int64_t la, int64_t lb, Plan pl, Work w) {
@@ -540,35 +520,34 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
             w.ctr->leaf_elems = (unsigned long long)S;
         }
     }
-    if (threadIdx.x < 6) {
-        const int q = threadIdx.x;
+    // the six searches, one wave each, 64 probes per dependent round
+    const int q = threadIdx.x >> 6;
+    if (q < 6) {
+        uint32_t rounds = 0;
         int64_t r = -1;
         if (q < 2) {
             // co-rank of diagonal d0 (q = 0) or d1 (q = 1)
             const int64_t d = q == 0 ? d0 : d1;
-            int64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
-            while (lo < hi) {
-                const int64_t m = lo + ((hi - lo) >> 1);
-                if (A[m] <= B[d - 1 - m]) lo = m + 1;
-                else hi = m;
-            }
-            r = lo;
+            const int64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+            r = group_search<64>(lo, hi, [&](int64_t m) { return A[m] <= B[d - 1 - m]; }, rounds);
         } else if (q < 4) {
             // output tile of the window's first / last A element
             const int64_t x0 = d0, x1 = d1 < la ? d1 : la;
             if (x0 < x1) {
                 const int64_t x = q == 2 ? x0 : x1 - 1;
-                r = (x + count_below(B, lb, A[x])) / T;
+                const K v = A[x];
+                r = (x + group_search<64>(0, lb, [&](int64_t m) { return B[m] < v; }, rounds)) / T;
             }
         } else {
             // output tile of the window's first / last B element
             const int64_t y0 = (d0 > la ? d0 : la) - la, y1 = d1 - la;
             if (y0 < y1) {
                 const int64_t y = q == 4 ? y0 : y1 - 1;
-                r = (y + count_at_most(A, la, B[y])) / T;
+                const K v = B[y];
+                r = (y + group_search<64>(0, la, [&](int64_t m) { return A[m] <= v; }, rounds)) / T;
             }
         }
-        s_geo[q] = r;
+        if ((threadIdx.x & 63) == 0) s_geo[q] = r;
     }
     __syncthreads();
     const int64_t ia0 = uniform64(s_geo[0]), ia1 = uniform64(s_geo[1]);
