@@ -638,6 +638,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device 3 times (the known-size "
                          "reference that scales the HBM byte counters) and exit")
+    ap.add_argument("--then-copy-probe", action="store_true",
+                    help="after the benchmark line, the same three 1 GiB copies (one "
+                         "counter run then holds the merge and its scale reference)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -655,12 +658,16 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     im.load()
     dev = torch.device("cuda:0")
-    if args.copy_probe:
+    def copy_probe():
         src = torch.ones(2 ** 28, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
+
+    if args.copy_probe:
+        copy_probe()
         print(json.dumps({"copy_probe_bytes_per_copy": 2 ** 30}), flush=True)
         return
 
@@ -724,6 +731,10 @@ def main():
         "forms": forms,
     }
     print(json.dumps(line), flush=True)
+    if args.then_copy_probe:
+        torch.cuda.empty_cache()
+        copy_probe()
+        log("copy probe: three device-to-device copies of 1 GiB")
 
 
 if __name__ == "__main__":
