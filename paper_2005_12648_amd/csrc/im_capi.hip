@@ -407,7 +407,7 @@ size_t carve(const Plan &pl, int64_t flag_slots, void *base, Work *w) {
     x.tile_start = (int64_t *)take(sizeof(int64_t) * pl.cap_leaves);
     x.tile_rank = (int64_t *)take(sizeof(int64_t) * pl.cap_tiles);
     x.tile_leaf = (int32_t *)take(sizeof(int32_t) * pl.cap_tiles);
-    x.tile_dep = (int32_t *)take(sizeof(int32_t) * 4 * pl.cap_tiles);
+    x.tile_geo = (TileGeo *)take(sizeof(TileGeo) * pl.cap_tiles);
     x.offsets1 = (int64_t *)take(sizeof(int64_t) * 4);
     x.cs_stash_k = nullptr;
     x.cs_stash_v = nullptr;

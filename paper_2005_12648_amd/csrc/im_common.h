@@ -156,6 +156,20 @@ constexpr int kCsLanes = 256;    // lanes per circular-shifting work item
 
 constexpr int kLeafCfgs = 4;   // leaf-merge tile configurations (im_leaf.hip)
 
+// Geometry of one leaf tile, in the order the leaf pipeline takes its slots
+// (written by the planning kernel, read in one round by the pipeline):
+// output window [out0, out0+n), A-slice (na elements from a0) and B-slice
+// (n - na elements from b0), all as element indices of the whole buffer; the
+// leaf's first tile and tile count, the tile's leaf-local index, and the
+// leaf-local tiles that read its window (A-slices [alo, ahi], B-slices
+// [blo, bhi]; an empty range is [0, -1]).
+struct TileGeo {
+    int64_t out0, a0, b0, tbase;
+    int n, na;
+    int32_t ntiles, local;
+    int32_t alo, ahi, blo, bhi;
+};
+
 // Workspace carve-up (device pointers).
 struct Work {
     Counters *ctr;
@@ -165,7 +179,7 @@ struct Work {
     int64_t *tile_start;     // per leaf: first tile index (exclusive scan)
     int64_t *tile_rank;      // per tile: co-rank at the tile's first diagonal
     int32_t *tile_leaf;      // per tile: its leaf
-    int32_t *tile_dep;       // per tile: leaf-local tiles reading its window, A [lo, hi], B [lo, hi]
+    TileGeo *tile_geo;       // per slot: the tile's geometry and readers
     unsigned int *tile_flag; // per tile: == epoch once its inputs are in LDS
     int64_t *offsets1;       // [3] offsets of a single-instance call
     void *cs_stash_k;        // circular shifting: first value of each cycle segment

@@ -13,7 +13,8 @@
 //      of the same leaf.  Every tile publishes "inputs read" in its own flag
 //      as soon as its slices are in LDS; before storing, a tile waits for
 //      the flags of exactly the tiles that read its window (k_tiledeps
-//      computes them from the co-ranks: the tiles whose A-slices meet the
+//      computes them from the co-ranks, with the rest of the tile's
+//      geometry, into one record per slot: the tiles whose A-slices meet the
 //      window's A elements and those whose B-slices meet its B elements,
 //      two contiguous ranges of a few tiles each; A elements only move
 //      right and B elements only move left, so the first range starts at or
@@ -58,17 +59,6 @@ __device__ __forceinline__ K key_max() {
     return std::numeric_limits<K>::max();
 }
 
-// Geometry of one tile: output window [out0, out0+n), A-slice (na elements
-// from a0) and B-slice (n - na elements from b0), all as element indices of
-// the whole buffer; its leaf's tile range and the range of tiles that read
-// its window.
-struct TileGeo {
-    int64_t out0, a0, b0, tbase;
-    int n, na;
-    int32_t ntiles, local;
-    int32_t alo, ahi, blo, bhi;   // readers: A-slices [alo, ahi], B-slices [blo, bhi]
-};
-
 // The slot index is the same in every lane: the geometry is read once per
 // wave and kept in scalar registers.
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
@@ -81,44 +71,22 @@ __device__ __forceinline__ int32_t uniform32(int32_t v) {
 }
 
 // Geometry of the tile processed in slot s (the slot order reverses the
-// tiles of a dir-1 leaf).
-__device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t s, int T) {
+// tiles of a dir-1 leaf): one record, its loads issued together.
+__device__ __forceinline__ TileGeo tile_geo(const Work &w, int64_t s) {
+    const TileGeo *r = w.tile_geo + uniform64(s);
     TileGeo g;
-    s = uniform64(s);
-    const int32_t l = uniform32(w.tile_leaf[s]);
-    const Leaf lf = w.leaves[l];
-    const int64_t base = uniform64(lf.base), la = uniform64(lf.la), lb = uniform64(lf.lb);
-    const int32_t ntiles = uniform32(lf.ntiles), dir = uniform32(lf.dir);
-    const int64_t tstart = uniform64(w.tile_start[l]);
-    const int64_t sl = s - tstart;
-    const int64_t local = dir ? (int64_t)ntiles - 1 - sl : sl;
-    const int64_t t = tstart + local;
-    const int64_t S = la + lb;
-    const int64_t d0 = local * (int64_t)T;
-    const int64_t d1 = d0 + T < S ? d0 + T : S;
-    const int n = (int)(d1 - d0);
-    const int64_t ia0 = uniform64(w.tile_rank[t]);
-    const int64_t ia1 = (local + 1 < ntiles) ? uniform64(w.tile_rank[t + 1]) : la;
-    // For ascending runs na = ia1 - ia0 already lies in this interval; the
-    // clamp only keeps every access inside the leaf when a caller passes
-    // unsorted runs (then the result is an unspecified permutation).
-    int64_t na64 = ia1 - ia0;
-    const int64_t na_lo = (d1 - lb - ia0) > 0 ? (d1 - lb - ia0) : 0;
-    const int64_t na_hi = (la - ia0) < (int64_t)n ? (la - ia0) : (int64_t)n;
-    if (na64 < na_lo) na64 = na_lo;
-    if (na64 > na_hi) na64 = na_hi;
-    g.out0 = base + d0;
-    g.n = n;
-    g.na = (int)na64;
-    g.a0 = base + ia0;                     // A elements before the window: ia0
-    g.b0 = base + la + (d0 - ia0);         // B elements before the window: d0 - ia0
-    g.ntiles = ntiles;
-    g.tbase = tstart;
-    g.local = (int32_t)local;
-    g.alo = uniform32(w.tile_dep[4 * t]);
-    g.ahi = uniform32(w.tile_dep[4 * t + 1]);
-    g.blo = uniform32(w.tile_dep[4 * t + 2]);
-    g.bhi = uniform32(w.tile_dep[4 * t + 3]);
+    g.out0 = uniform64(r->out0);
+    g.a0 = uniform64(r->a0);
+    g.b0 = uniform64(r->b0);
+    g.tbase = uniform64(r->tbase);
+    g.n = uniform32(r->n);
+    g.na = uniform32(r->na);
+    g.ntiles = uniform32(r->ntiles);
+    g.local = uniform32(r->local);
+    g.alo = uniform32(r->alo);
+    g.ahi = uniform32(r->ahi);
+    g.blo = uniform32(r->blo);
+    g.bhi = uniform32(r->bhi);
     return g;
 }
 
@@ -241,10 +209,12 @@ struct LeafOps {
 
     // Merge the tile held in LDS into registers (stable: ties take A), then
     // transpose through LDS so that thread p holds outputs p + u*THREADS
-    // (coalesced stores).  Leaves the LDS free.
-    template <bool MATERIALISE>
+    // (coalesced stores).  Leaves the LDS free.  `before_last_sync` runs
+    // before the closing barrier (the pipeline hands its next slot over
+    // there instead of with a barrier of its own).
+    template <bool MATERIALISE, typename Pre>
     static __device__ __forceinline__ void merge(const TileGeo &g, K *sk, V *sv, K (&out)[IPT],
-                                                 V (&vout)[VN]) {
+                                                 V (&vout)[VN], Pre before_last_sync) {
         const int tid = threadIdx.x;
         const int n = g.n, na = g.na, nb = g.n - g.na;
         {
@@ -257,31 +227,42 @@ struct LeafOps {
                 if (sk[mid] <= sk[na + d - 1 - mid]) lo = mid + 1;
                 else hi = mid;
             }
-            // ia: next A index, bi: LDS index of the next B element.  A
-            // sentinel (the key type's maximum) follows B, so an exhausted B
-            // never wins (a <= max, and ties take A anyway); an exhausted A
-            // is tested by index.  Steps past the tile end (last thread) read
-            // the padding and their outputs are not stored.
-            int ia = lo, bi = na + (d - lo);
-            K a = sk[ia];
-            K b = sk[bi];
+            // qa, qb: the next A and the next B element in LDS.  A sentinel
+            // (the key type's maximum) follows B, so an exhausted B never
+            // wins (a <= max, and ties take A anyway); an exhausted A is
+            // tested by position, but only in a wave where some lane can
+            // reach the end of A within its IPT steps (lane 63 starts
+            // furthest along A): elsewhere a <= b alone decides.  Steps past
+            // the tile end (last thread) read the padding and their outputs
+            // are not stored.
+            const K *qa = sk + lo;
+            const K *qb = sk + (na + (d - lo));
+            const K *const qa_end = sk + na;
+            K a = *qa;
+            K b = *qb;
+            const bool a_may_end = __builtin_amdgcn_readlane(lo, 63) + IPT > na;
             // branch-free steps (selects only): no per-step exec masks
-#pragma unroll
-            for (int e = 0; e < IPT; ++e) {
-                const bool ta = (ia < na) && (a <= b);
+            auto step = [&](int e, bool ta) {
                 K o = ta ? a : b;
                 // With two register sets live (depth 3), materialise the
                 // output now: otherwise the select is sunk to its use and
                 // both candidates plus the mask stay live, which spills.
                 if constexpr (MATERIALISE) asm volatile("" : "+v"(o));
                 out[e] = o;
-                const int src = ta ? ia : bi;
-                if constexpr (HAS_V) vout[e] = sv[src];
-                const K v = sk[src + 1];
-                ia += ta ? 1 : 0;
-                bi += ta ? 0 : 1;
+                const K *q = ta ? qa : qb;
+                if constexpr (HAS_V) vout[e] = sv[q - sk];
+                const K v = q[1];
+                qa = ta ? q + 1 : qa;
+                qb = ta ? qb : q + 1;
                 a = ta ? v : a;
                 b = ta ? b : v;
+            };
+            if (a_may_end) {
+#pragma unroll
+                for (int e = 0; e < IPT; ++e) step(e, (qa < qa_end) && (a <= b));
+            } else {
+#pragma unroll
+                for (int e = 0; e < IPT; ++e) step(e, a <= b);
             }
         }
         __syncthreads();                     // LDS inputs of this tile are dead
@@ -306,6 +287,7 @@ struct LeafOps {
                 if constexpr (HAS_V) vout[u] = sv[x];
             }
         }
+        before_last_sync();
         __syncthreads();
     }
 
@@ -377,12 +359,19 @@ __device__ __forceinline__ bool leaf_step(K *keys, V *vals, K *sk, V *sv, const 
                                           K (&cur)[IPT], V (&vcur)[LeafOps<K, V, THREADS, IPT>::VN],
                                           K (&nxt)[IPT], V (&vnxt)[LeafOps<K, V, THREADS, IPT>::VN]) {
     using Ops = LeafOps<K, V, THREADS, IPT>;
-    if (p.has1) Ops::template merge<true>(p.g1, sk, sv, nxt, vnxt);
-    const int64_t t2 = hand_over(s_slot, pend, p.first, p.ntiles, p.has1);
+    // the slot taken last step (thread 0's `pend`) reaches every thread
+    // through LDS at the merge's closing barrier
+    int64_t t2 = p.ntiles;
+    if (p.has1) {
+        Ops::template merge<true>(p.g1, sk, sv, nxt, vnxt, [&] {
+            if (threadIdx.x == 0) s_slot[0] = p.first + (int64_t)pend;
+        });
+        t2 = uniform64(s_slot[0]);
+    }
     const bool has2 = p.has1 && t2 < p.ntiles;
     TileGeo g2 = p.g1;
     if (has2) {
-        g2 = tile_geo(w, t2, Ops::T);
+        g2 = tile_geo(w, t2);
         Ops::stage(keys, vals, g2, sk, sv, pl, w);
     }
     const bool ready = Ops::wait_readers(p.g, pl, w);
@@ -428,19 +417,21 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
 
     K ra[IPT];
     V va[Ops::VN];
-    p.g = tile_geo(w, t0, Ops::T);
+    p.g = tile_geo(w, t0);
     Ops::stage(keys, vals, p.g, sk, sv, pl, w);
     if constexpr (DEPTH == 2) {
         p.first = G;
         bool more = t0 + G < p.ntiles;
         if (threadIdx.x == 0 && more) pend = take_slot(w);
         for (;;) {
-            Ops::template merge<false>(p.g, sk, sv, ra, va);
-            const int64_t tn = hand_over(s_slot, pend, p.first, p.ntiles, more);
+            Ops::template merge<false>(p.g, sk, sv, ra, va, [&] {
+                if (threadIdx.x == 0) s_slot[0] = more ? p.first + (int64_t)pend : p.ntiles;
+            });
+            const int64_t tn = uniform64(s_slot[0]);
             const bool has_next = tn < p.ntiles;
             TileGeo gn = p.g;
             if (has_next) {
-                gn = tile_geo(w, tn, Ops::T);
+                gn = tile_geo(w, tn);
                 Ops::stage(keys, vals, gn, sk, sv, pl, w);
             }
             const bool ready = Ops::wait_readers(p.g, pl, w);
@@ -455,11 +446,11 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
         V vb[Ops::VN];
         // prologue: b into registers, b+G into LDS, the next slot taken
         p.first = 2 * G;
-        Ops::template merge<true>(p.g, sk, sv, ra, va);
+        Ops::template merge<true>(p.g, sk, sv, ra, va, [] {});
         p.has1 = t0 + G < p.ntiles;
         p.g1 = p.g;
         if (p.has1) {
-            p.g1 = tile_geo(w, t0 + G, Ops::T);
+            p.g1 = tile_geo(w, t0 + G);
             Ops::stage(keys, vals, p.g1, sk, sv, pl, w);
             if (threadIdx.x == 0) pend = take_slot(w);
         }
@@ -553,7 +544,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
     const int64_t ia0 = uniform64(s_geo[0]), ia1 = uniform64(s_geo[1]);
     TileGeo g;
     const int n = (int)(d1 - d0);
-    int64_t na64 = ia1 - ia0;    // clamped as in tile_geo (only unsorted input needs it)
+    int64_t na64 = ia1 - ia0;    // clamped as the planning kernel does (only unsorted input needs it)
     const int64_t na_lo = (d1 - lb - ia0) > 0 ? (d1 - lb - ia0) : 0;
     const int64_t na_hi = (la - ia0) < (int64_t)n ? (la - ia0) : (int64_t)n;
     if (na64 < na_lo) na64 = na_lo;
@@ -575,7 +566,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
     Ops::stage(keys, vals, g, sk, sv, pl, w);
     K out[IPT];
     V vout[Ops::VN];
-    Ops::template merge<false>(g, sk, sv, out, vout);
+    Ops::template merge<false>(g, sk, sv, out, vout, [] {});
     if (Ops::wait_readers(g, pl, w)) Ops::store(keys, vals, g, out, vout);
 }
 
@@ -714,7 +705,7 @@ __device__ __forceinline__ bool row_step(unsigned char *data, const RowGeo &rg, 
     const bool has = tn < ntiles;
     TileGeo gn = g;
     if (has) {
-        gn = tile_geo(w, tn, rg.R);
+        gn = tile_geo(w, tn);
         RowOps<K, CH>::read(data, rg, gn, sk, so, nxt, pl, w);
     }
     const bool ready = wait_window<kRowThreads>(g, pl, w);
@@ -739,7 +730,7 @@ __global__ __launch_bounds__(kRowThreads, 4) void k_leafrows(unsigned char *__re
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
     typename Ops::C ra[Ops::CPT], rb[Ops::CPT];
-    TileGeo g = tile_geo(w, t, rg.R);
+    TileGeo g = tile_geo(w, t);
     Ops::read(data, rg, g, sk, so, ra, pl, w);
     bool more = t + gridDim.x < ntiles;
     unsigned long long pend = 0;
@@ -854,7 +845,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_merge_oop(const K *__restrict__ 
     __syncthreads();
     K r[IPT];
     NoValL v[1];
-    Ops::template merge<false>(g, sk, nullptr, r, v);
+    Ops::template merge<false>(g, sk, nullptr, r, v, [] {});
     Ops::store(out, nullptr, g, r, v);
 }
 
@@ -910,7 +901,10 @@ hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int6
 // the first j with jb(j+1) > pb0 to the last j with jb(j) < pb1.  An empty
 // range is stored as [0, -1].  (Every tile between the window and its last
 // reader used to be polled as well: hundreds of device-scope flag loads per
-// tile on large leaves, against a handful.)
+// tile on large leaves, against a handful.)  Each tile's whole geometry goes
+// into the record of the slot that processes it, so that the pipeline reads
+// one record in one round of loads (it used to follow tile -> leaf -> co-rank
+// -> readers, three dependent rounds, about a tenth of a pipeline step).
 __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
     int64_t ntiles = (int64_t)w.ctr->tiles;
     if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
@@ -959,10 +953,35 @@ __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
             if (has_a) { alo = lo0; ahi = lo1; }
             if (has_b) { blo = lo2; bhi = lo3; }
         }
-        w.tile_dep[4 * t] = (int32_t)alo;
-        w.tile_dep[4 * t + 1] = (int32_t)ahi;
-        w.tile_dep[4 * t + 2] = (int32_t)blo;
-        w.tile_dep[4 * t + 3] = (int32_t)bhi;
+        // the record of the slot that processes tile t (a dir-1 leaf takes
+        // its tiles in decreasing order)
+        const int64_t d0 = i * T;
+        const int64_t d1 = d0 + T < S ? d0 + T : S;
+        const int64_t n = d1 - d0;
+        const int64_t ia0 = w.tile_rank[t];
+        const int64_t ia1 = i + 1 < nt ? w.tile_rank[t + 1] : lf.la;
+        // For ascending runs na = ia1 - ia0 already lies in this interval; the
+        // clamp only keeps every access inside the leaf when a caller passes
+        // unsorted runs (then the result is an unspecified permutation).
+        int64_t na = ia1 - ia0;
+        const int64_t na_lo = (d1 - lf.lb - ia0) > 0 ? (d1 - lf.lb - ia0) : 0;
+        const int64_t na_hi = (lf.la - ia0) < n ? (lf.la - ia0) : n;
+        if (na < na_lo) na = na_lo;
+        if (na > na_hi) na = na_hi;
+        TileGeo g;
+        g.out0 = lf.base + d0;
+        g.a0 = lf.base + ia0;                    // A elements before the window: ia0
+        g.b0 = lf.base + lf.la + (d0 - ia0);     // B elements before the window: d0 - ia0
+        g.tbase = ts;
+        g.n = (int)n;
+        g.na = (int)na;
+        g.ntiles = (int32_t)nt;
+        g.local = (int32_t)i;
+        g.alo = (int32_t)alo;
+        g.ahi = (int32_t)ahi;
+        g.blo = (int32_t)blo;
+        g.bhi = (int32_t)bhi;
+        w.tile_geo[ts + (lf.dir ? nt - 1 - i : i)] = g;
     }
 }
 
