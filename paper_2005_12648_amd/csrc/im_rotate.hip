@@ -586,8 +586,10 @@ static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, i
     // 512-thread workgroups (grid-stride items): a grid several times larger
     // than the chip holds at once, so that workgroups that finish early are
     // replaced, which balances the items.  (Measured on the exchange stage
-    // of 2^28-element merges, grids of 768 ... 16384: exactly the resident
-    // workgroups is 6-13% slower than 2048; 6144 is best, -6% against 2048.)
+    // of the 2^27+2^27 int32 merge, about 16k items per level: grids of
+    // 6144 / 12288 / 16384 / 24576 / 32768 take 0.490 / 0.480 / 0.473 /
+    // 0.483 / 0.498 ms, the empty launches included; exactly the resident
+    // workgroups was 6-13% slower than 2048 in an earlier version.)
     // 1024-thread workgroups take items from a counter, which balances them
     // without replacement: 1024 (best of 1024, 2048 and 4096).  Phase 1 (the
     // last reversal of three-reversal exchanges) is empty on balanced levels,
@@ -595,7 +597,7 @@ static hipError_t rot_t(void *keys, void *vals, const Plan &pl, const Work &w, i
     // (measured: int32 2^27+2^27 merge -0.7%, 64-byte rows -1.2%, the
     // 4096-instance batch, which has phase-1 work, unchanged).
     constexpr int TH = RotGeom<(int)sizeof(EK) + ValBytes<EV>::v>::threads;
-    const int g = phase == 1 ? 1024 : (TH == 512 ? 6144 : 1024);
+    const int g = phase == 1 ? 1024 : (TH == 512 ? 16384 : 1024);
     hipLaunchKernelGGL((k_rotate<EK, EV>), dim3(g), dim3(TH), 0, s, (EK *)keys, (EV *)vals,
                        w.rot, w.ctr, pl.cap_rot, level, phase);
     return hipGetLastError();
