@@ -110,10 +110,11 @@ int inplace_merge(void *data, int64_t L_A, int64_t L_B, int dtype, hipStream_t s
  * hipFree, pinned-host or event allocation: its workspace is a static
  * device array of 4 MiB that the library holds on every device it runs on
  * until the process ends.  The result equals inplace_merge()'s.  A merge
- * whose workspace (descriptors, counters, tile flags: about 32 bytes per
- * 17,920 int32 or 8,704 int64 elements, plus a few KiB) does not fit in the
- * array is refused with IM_ERR_WORKSPACE before any work is enqueued (int32
- * inputs of a few 10^9 elements fit).  Every call on a device shares that
+ * whose workspace (descriptors, counters, per-tile co-ranks, flags and
+ * geometry: about 80 bytes per 16,896 int32 or 8,704 int64 elements, plus a
+ * few KiB) does not fit in the array is refused with IM_ERR_WORKSPACE before
+ * any work is enqueued (int32 inputs of up to about 8*10^8 elements, int64
+ * of about 4*10^8, fit).  Every call on a device shares that
  * device's array and leaves its last contents there: two such calls whose
  * work overlaps in time on one device (different streams, or different host
  * threads without ordering) race and give wrong results; calls on one
@@ -319,7 +320,7 @@ int inplace_merge_sort(void *data, int64_t n, int dtype, hipStream_t stream);
  * of an in-place merge sort of N).  The library allocates its workspace
  * lazily per device if none is set.  The workspace holds split descriptors
  * and counters only: its size grows with the number of workgroup tiles,
- * never with the data itself (about 0.3 MB for 2^28 int32 elements).
+ * never with the data itself (about 1.3 MB for 2^28 int32 elements).
  * Returns 0 for invalid arguments. */
 size_t inplace_merge_workspace_bytes(int64_t N, int dtype);
 

@@ -21,7 +21,7 @@
 //      after the tile and the second ends at or before it);
 //   5. coalesced store of the window.
 // The grid is persistent and co-resident (cooperative launch).  Workgroup b
-// takes slots b and b+G (b alone at depth 2) and then further slots from a
+// takes slots b, b+G, ..., b+(depth-1)G and then further slots from a
 // device counter, in increasing order, each after the wait of the step
 // before the slot is staged.  Within a leaf the slots visit the tiles in
 // increasing order when every A element moves right by at most the leaf
@@ -29,15 +29,15 @@
 // the leaf capacity), else in decreasing order (then its A-part is within
 // the span and every B element moves left by at most the span).  The
 // planner keeps every reader less than depth*G slots after the tile it
-// reads.  Deadlock freedom (depth 3): suppose every workgroup that still has
+// reads.  Deadlock freedom (depth d): suppose every workgroup that still has
 // tiles waits, and let s be the smallest slot not yet stored.  A waiting
-// workgroup has staged every slot it holds: the one it waits to store, one
-// merged into a second register set and one staged in LDS, all at or after
+// workgroup has staged every slot it holds: the one it waits to store, d-2
+// merged into further register sets and one staged in LDS, all at or after
 // s.  Either every slot has been handed out (and so staged), or each
-// workgroup holds three, and the contiguous handed-out range reaches at
-// least s+3G.  Either way the readers of s's window, less than 3G slots
-// after s, have read their inputs, so s is stored.  The wait is bounded: on
-// expiry the workgroup raises an error bit and skips its store.
+// workgroup holds d, and the contiguous handed-out range reaches at least
+// s+dG.  Either way the readers of s's window, less than dG slots after s,
+// have read their inputs, so s is stored.  The wait is bounded: on expiry
+// the workgroup raises an error bit and skips its store.
 #include <limits>
 #include <type_traits>
 #include "im_common.h"
@@ -153,28 +153,46 @@ __device__ __forceinline__ void buf_store(E v, __amdgpu_buffer_rsrc_t r, int off
 
 __device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// The tile whose bounded wait expired in some thread of the workgroup
+// (its tile index; -1 before any).  Every kernel that waits sets it to -1
+// before its first barrier.
+__shared__ int64_t s_expired;
+
+__device__ __forceinline__ void init_wait_state() {
+    if (threadIdx.x == 0) s_expired = -1;
+}
+
 // Wait until every tile that reads this window has its inputs on chip.
 // Flags are touched only with relaxed device-scope atomics: the readers'
 // loads have returned before they publish, and an acquire/release fence at
 // device scope would write back or invalidate this XCD's whole L2 on every
-// poll.  Returns false if the bounded wait expired.
+// poll.  Returns false if the bounded wait expired: a thread whose wait
+// expires writes the tile's index into s_expired, and after the barrier the
+// whole workgroup sees it (a plain barrier and one LDS read instead of a
+// workgroup reduction).
 template <int THREADS>
 __device__ __forceinline__ bool wait_window(const TileGeo &g, const Plan &pl, const Work &w) {
     if (g.ntiles <= 1) return true;
     const int na = g.ahi >= g.alo ? g.ahi - g.alo + 1 : 0;
     const int nb = g.bhi >= g.blo ? g.bhi - g.blo + 1 : 0;
-    int bad = 0;
-    for (int x = (int)threadIdx.x; x < na + nb && !bad; x += THREADS) {
+    const int64_t tag = g.tbase + g.local;
+    for (int x = (int)threadIdx.x; x < na + nb; x += THREADS) {
         const int q = x < na ? g.alo + x : g.blo + (x - na);
         if (q == g.local) continue;
         const unsigned *f = &w.tile_flag[g.tbase + q];
         unsigned spins = 0;
+        bool expired = false;
         while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pl.epoch) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) { bad = 1; break; }
+            if (++spins > kSpinLimit) { expired = true; break; }
+        }
+        if (expired) {
+            s_expired = tag;
+            break;
         }
     }
-    bad = __syncthreads_or(bad);
+    __syncthreads();
+    const bool bad = s_expired == tag;
     if (bad && threadIdx.x == 0) raise_error(w, kErrBarrierSpin);
     return !bad;
 }
@@ -342,11 +360,12 @@ __device__ __forceinline__ int64_t hand_over(int64_t *s_slot, unsigned long long
 }
 
 // Pipeline state of one workgroup: tile g (merged, in registers `cur`),
-// tile g1 (staged in LDS), and whether g1 exists.
+// at depth 4 tile gm (merged, in a second register set), tile g1 (staged in
+// LDS), and whether gm and g1 exist.
 struct LeafPipe {
-    int64_t ntiles, first;  // tiles; first slot handed out by the counter (2G)
-    bool has1;
-    TileGeo g, g1;
+    int64_t ntiles, first;  // tiles; first slot handed out by the counter ((DEPTH-1)*G)
+    bool hasm, has1;
+    TileGeo g, gm, g1;
 };
 
 // One step: merge g1 from LDS into `nxt`, stage the slot taken last step
@@ -384,7 +403,42 @@ __device__ __forceinline__ bool leaf_step(K *keys, V *vals, K *sk, V *sv, const 
     return true;
 }
 
-// Pipeline per workgroup (its static slots b and b+G, then slots from the
+// Depth-4 step: as leaf_step, with one more merged tile held in a third
+// register set (`mid`) between the one stored this step and the one merged
+// this step.  The three sets rotate roles from step to step.
+template <typename K, typename V, int THREADS, int IPT>
+__device__ __forceinline__ bool leaf_step4(K *keys, V *vals, K *sk, V *sv, const Plan &pl,
+                                           const Work &w, LeafPipe &p, int64_t *s_slot,
+                                           unsigned long long &pend,
+                                           K (&cur)[IPT], V (&vcur)[LeafOps<K, V, THREADS, IPT>::VN],
+                                           K (&nxt)[IPT], V (&vnxt)[LeafOps<K, V, THREADS, IPT>::VN]) {
+    using Ops = LeafOps<K, V, THREADS, IPT>;
+    int64_t t2 = p.ntiles;
+    if (p.has1) {
+        Ops::template merge<true>(p.g1, sk, sv, nxt, vnxt, [&] {
+            if (threadIdx.x == 0) s_slot[0] = p.first + (int64_t)pend;
+        });
+        t2 = uniform64(s_slot[0]);
+    }
+    const bool has2 = p.has1 && t2 < p.ntiles;
+    TileGeo g2 = p.g1;
+    if (has2) {
+        g2 = tile_geo(w, t2);
+        Ops::stage(keys, vals, g2, sk, sv, pl, w);
+    }
+    const bool ready = Ops::wait_readers(p.g, pl, w);
+    if (threadIdx.x == 0 && has2) pend = take_slot(w);
+    if (ready) Ops::store(keys, vals, p.g, cur, vcur);
+    if (!p.hasm) return false;
+    p.g = p.gm;
+    p.hasm = p.has1;
+    p.gm = p.g1;
+    p.has1 = has2;
+    p.g1 = g2;
+    return true;
+}
+
+// Pipeline per workgroup (its static slots b, b+G, ..., then slots from the
 // counter; the deadlock argument at the top of this file holds because the
 // slots handed out are contiguous and every waiting workgroup holds `depth`
 // staged slots, so the slots staged when all wait reach depth*G past the
@@ -397,15 +451,18 @@ __device__ __forceinline__ bool leaf_step(K *keys, V *vals, K *sk, V *sv, const 
 //            into LDS and flagged: readers may be up to 3G-1 slots ahead
 //            (larger leaves, fewer division levels), at the price of a
 //            second register set.
+//   DEPTH 4: as depth 3 with a third register set holding one more merged
+//            tile: readers may be up to 4G-1 slots ahead.
 template <typename K, typename V, int THREADS, int IPT, int DEPTH>
 __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
                                                           Plan pl, Work w) {
     using Ops = LeafOps<K, V, THREADS, IPT>;
-    static_assert(DEPTH == 2 || DEPTH == 3, "pipeline depth");
+    static_assert(DEPTH >= 2 && DEPTH <= 4, "pipeline depth");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_slot[1];
     K *sk = reinterpret_cast<K *>(smem);
     V *sv = reinterpret_cast<V *>(smem + (size_t)Ops::PE * sizeof(K));
+    init_wait_state();
 
     LeafPipe p;
     p.ntiles = (int64_t)w.ctr->tiles;
@@ -440,6 +497,39 @@ __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, 
             if (!has_next) break;
             more = true;
             p.g = gn;
+        }
+    } else if constexpr (DEPTH == 4) {
+        K rb[IPT], rc[IPT];
+        V vb[Ops::VN], vc[Ops::VN];
+        // prologue: b and b+G into registers, b+2G into LDS, the next slot taken
+        p.first = 3 * G;
+        Ops::template merge<true>(p.g, sk, sv, ra, va, [] {});
+        p.hasm = t0 + G < p.ntiles;
+        p.gm = p.g;
+        p.has1 = false;
+        p.g1 = p.g;
+        if (p.hasm) {
+            p.gm = tile_geo(w, t0 + G);
+            Ops::stage(keys, vals, p.gm, sk, sv, pl, w);
+            Ops::template merge<true>(p.gm, sk, sv, rb, vb, [] {});
+            p.has1 = t0 + 2 * G < p.ntiles;
+            if (p.has1) {
+                p.g1 = tile_geo(w, t0 + 2 * G);
+                Ops::stage(keys, vals, p.g1, sk, sv, pl, w);
+                if (threadIdx.x == 0) pend = take_slot(w);
+            }
+        }
+        // the three register sets rotate roles: stored, held, merged into
+        for (;;) {
+            if (!leaf_step4<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, s_slot, pend, ra, va,
+                                                rc, vc))
+                break;
+            if (!leaf_step4<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, s_slot, pend, rb, vb,
+                                                ra, va))
+                break;
+            if (!leaf_step4<K, V, THREADS, IPT>(keys, vals, sk, sv, pl, w, p, s_slot, pend, rc, vc,
+                                                rb, vb))
+                break;
         }
     } else {
         K rb[IPT];
@@ -492,6 +582,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
     __shared__ int64_t s_geo[6];
     K *sk = reinterpret_cast<K *>(smem);
     V *sv = reinterpret_cast<V *>(smem + (size_t)Ops::PE * sizeof(K));
+    init_wait_state();
     const int64_t S = la + lb, T = Ops::T;
     const int64_t ntiles = (S + T - 1) / T;
     const int64_t t = blockIdx.x;
@@ -727,6 +818,7 @@ __global__ __launch_bounds__(kRowThreads, 4) void k_leafrows(unsigned char *__re
     int64_t ntiles = (int64_t)w.ctr->tiles;
     if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
     __shared__ int64_t s_slot[1];
+    init_wait_state();
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
     typename Ops::C ra[Ops::CPT], rb[Ops::CPT];
@@ -1013,7 +1105,12 @@ hipError_t launch_fill32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
 // Items per thread are odd, so the blocked LDS accesses are bank-conflict
 // free.
 //   config 0: 8 waves per tile, about 70 KB of LDS (two workgroups fill a
-//             CU), pipeline depth 3: the largest leaves
+//             CU), pipeline depth 3 -- depth 4 for 4-byte keys, whose three
+//             register sets of 33 items still fit the 128 registers a lane
+//             has at two workgroups per CU: the largest leaves.  (Measured
+//             on the 2^27+2^27 int32 merge: leaves of 2048 tiles of 16896
+//             hold the four 2^26-element nodes of the second level, so the
+//             third division level and its exchange go: 0.98 -> 0.84 ms.)
 //   config 1: as 0 with depth 2 (one register set, smaller leaves)
 //   config 2: 4 waves per tile, same items per thread (half the tile, four
 //             workgroups per CU), depth 2: finer grain for many instances
@@ -1029,6 +1126,10 @@ static void geom(int ek, int ev, int cfg, int *th, int *ipt, int *depth) {
     *th = cfg <= 1 ? 512 : 256;
     *ipt = cfg == 3 ? ipt_small(eb) : ipt_big(eb);
     *depth = (cfg == 0 || cfg == 3) ? 3 : 2;
+    if (cfg == 0 && eb <= 4) {
+        *ipt = 33;
+        *depth = 4;
+    }
 }
 
 void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, int *depth,
@@ -1039,26 +1140,27 @@ void leaf_geometry(int esize_k, int esize_v, int cfg, int *threads, int *ipt, in
     *lds_bytes = pe * esize_k + pe * esize_v;
 }
 
-// One line per (key, payload): the configurations' (threads, items, depth).
-#define IM_LEAF_KV(X, K, V, BIG, SMALL) \
-    X(K, V, 0, 512, BIG, 3)             \
-    X(K, V, 1, 512, BIG, 2)             \
-    X(K, V, 2, 256, BIG, 2)             \
+// One line per (key, payload): the configurations' (threads, items, depth),
+// config 0 with its own items and depth.
+#define IM_LEAF_KV(X, K, V, IPT0, DEPTH0, BIG, SMALL) \
+    X(K, V, 0, 512, IPT0, DEPTH0)                     \
+    X(K, V, 1, 512, BIG, 2)                           \
+    X(K, V, 2, 256, BIG, 2)                           \
     X(K, V, 3, 256, SMALL, 3)
 
-#define IM_LEAF_CASES(X)                        \
-    IM_LEAF_KV(X, int32_t, NoValL, 35, 17)      \
-    IM_LEAF_KV(X, uint32_t, NoValL, 35, 17)     \
-    IM_LEAF_KV(X, int64_t, NoValL, 17, 9)       \
-    IM_LEAF_KV(X, uint64_t, NoValL, 17, 9)      \
-    IM_LEAF_KV(X, int32_t, uint32_t, 17, 9)     \
-    IM_LEAF_KV(X, uint32_t, uint32_t, 17, 9)    \
-    IM_LEAF_KV(X, int64_t, uint32_t, 11, 5)     \
-    IM_LEAF_KV(X, uint64_t, uint32_t, 11, 5)    \
-    IM_LEAF_KV(X, int32_t, uint64_t, 11, 5)     \
-    IM_LEAF_KV(X, uint32_t, uint64_t, 11, 5)    \
-    IM_LEAF_KV(X, int64_t, uint64_t, 9, 5)      \
-    IM_LEAF_KV(X, uint64_t, uint64_t, 9, 5)
+#define IM_LEAF_CASES(X)                              \
+    IM_LEAF_KV(X, int32_t, NoValL, 33, 4, 35, 17)     \
+    IM_LEAF_KV(X, uint32_t, NoValL, 33, 4, 35, 17)    \
+    IM_LEAF_KV(X, int64_t, NoValL, 17, 3, 17, 9)      \
+    IM_LEAF_KV(X, uint64_t, NoValL, 17, 3, 17, 9)     \
+    IM_LEAF_KV(X, int32_t, uint32_t, 17, 3, 17, 9)    \
+    IM_LEAF_KV(X, uint32_t, uint32_t, 17, 3, 17, 9)   \
+    IM_LEAF_KV(X, int64_t, uint32_t, 11, 3, 11, 5)    \
+    IM_LEAF_KV(X, uint64_t, uint32_t, 11, 3, 11, 5)   \
+    IM_LEAF_KV(X, int32_t, uint64_t, 11, 3, 11, 5)    \
+    IM_LEAF_KV(X, uint32_t, uint64_t, 11, 3, 11, 5)   \
+    IM_LEAF_KV(X, int64_t, uint64_t, 9, 3, 9, 5)      \
+    IM_LEAF_KV(X, uint64_t, uint64_t, 9, 3, 9, 5)
 
 template <typename K> struct KeyOf;
 template <> struct KeyOf<int32_t> { static constexpr int code = kI32; };

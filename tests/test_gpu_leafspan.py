@@ -1,12 +1,13 @@
 """The leaf merge's read-ahead bound, checked against the CPU oracle.
 
-Every workgroup of the persistent leaf merge reads `depth` tiles (2 or 3,
-by configuration) ahead of its oldest unstored one, so a leaf may span up to
-depth x G tiles (G resident workgroups, the default capacity) and still never
-block for good.  The IM_LEAF_GRID hook shrinks G so that small inputs put
-readers up to depth x G - 1 slots ahead of the tiles they wait on
-(IM_LEAF_TILES=2G checks a smaller capacity); the full-size cases check
-balanced leaves between G and 3G tiles at the real grid.
+Every workgroup of the persistent leaf merge reads `depth` tiles (2, 3 or
+4, by configuration and element size) ahead of its oldest unstored one, so a
+leaf may span up to depth x G tiles (G resident workgroups, the default
+capacity) and still never block for good.  The IM_LEAF_GRID hook shrinks G so
+that small inputs put readers up to depth x G - 1 slots ahead of the tiles
+they wait on (IM_LEAF_TILES=2G checks a smaller capacity); the full-size
+cases check balanced leaves between G and 4G tiles at the real grid, one of
+them with readers more than 3G slots ahead.
 """
 import sys
 
@@ -41,7 +42,7 @@ def small_grid(monkeypatch):
 CASES = [(100_000, 90_001), (7, 200_000), (200_000, 7), (150_000, 150_000), (1, 1), (17_920, 17_921)]
 
 
-DEPTH = {0: 3, 1: 2, 2: 2, 3: 3}      # pipeline depth of each leaf configuration
+DEPTH = {0: 4, 1: 2, 2: 2, 3: 3}      # pipeline depth of each leaf configuration (int32 keys)
 
 
 @pytest.mark.parametrize("grid", [1, 2, 3, 5, 16])
@@ -67,7 +68,7 @@ def test_small_grid_pairs(dev, small_grid, grid, cfg):
 
 @pytest.mark.parametrize("grid", [1, 2, 3, 5])
 def test_small_grid_reduced_capacity(dev, small_grid, monkeypatch, grid):
-    # a capacity below the read-ahead limit of depth 3 (2G tiles per leaf)
+    # a capacity below the read-ahead limit of configuration 0 (2G tiles per leaf)
     small_grid(grid)
     im.set_config(0)
     monkeypatch.setenv("IM_LEAF_TILES", str(2 * grid))
@@ -115,10 +116,33 @@ def test_balanced_leaf_beyond_g_tiles(dev, half):
         say(st)
         G = st["leaf_grid"]
         assert st["leaves"] == 1 and st["levels_used"] <= 1
-        assert G * st["tile"] < la + lb <= 3 * G * st["tile"]
+        assert G * st["tile"] < la + lb <= st["leaf_capacity"]
         got = t.cpu().numpy()
         want = oracle.merge(data, la)
         assert np.array_equal(got, want)
+    finally:
+        im.set_config(-1)
+
+
+def test_balanced_leaf_readers_beyond_3g(dev):
+    # one leaf of 2^25 + 2^25 int32 at the real grid (the leaves of the
+    # 2^27 + 2^27 merge): the last windows of A are read by tiles about
+    # L_A / tile = 3.9 G slots ahead, which only depth 4 reaches
+    im.set_config(0)
+    try:
+        la = lb = 2 ** 25
+        data = gen.pair_uniform(la, lb, 4343)
+        t = d(data, dev)
+        im.inplace_merge(t, la)
+        st = im.fetch_stats()
+        say(st)
+        G = st["leaf_grid"]
+        assert st["leaves"] == 1 and st["levels_used"] <= 1
+        assert la > 3 * G * st["tile"]
+        got = t.cpu().numpy()
+        want = oracle.merge(data, la)
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, "%d mismatches, first at %d" % (bad.size, bad[0])
     finally:
         im.set_config(-1)
 

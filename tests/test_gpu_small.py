@@ -17,7 +17,7 @@ import paper_2005_12648_amd as im
 
 pytestmark = pytest.mark.gpu
 
-TILE32 = 512 * 35
+TILE32 = 512 * 33        # configuration-0 tiles: 512 threads x 33 (int32) or 17 (int64) items
 TILE64 = 512 * 17
 
 
