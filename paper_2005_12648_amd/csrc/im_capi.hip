@@ -260,6 +260,34 @@ int leaf_shift(const Plan &pl) {
     return tb + lb + 1 <= 64 ? tb : 0;
 }
 
+// Division levels: children are at most 9/16 of the parent (plus one for
+// rounding); a node of at most max(leaf_cap, 2*leaf_span) elements is a
+// leaf; the last level only classifies.
+int division_levels(const Plan &pl, int64_t max_inst) {
+    const double stop = (double)std::max<int64_t>(pl.leaf_cap, 2 * pl.leaf_span);
+    int lv = 1;
+    double sz = (double)max_inst;
+    while (sz > stop && lv < kMaxLevels) {
+        sz = sz * 9.0 / 16.0 + 1.0;
+        ++lv;
+    }
+    return lv;
+}
+
+// Descriptor capacities.  A node is split only when it exceeds the leaf
+// capacity, so a level has fewer than `per` split nodes; a level's node
+// list takes children of the level before (2 per split) and grandchildren of
+// fused nodes two levels before (4 per split); a fused node emits at most
+// kMaxCuts/2 cycles.  Cell tiles (Plan::cells) add up to one tile per leaf.
+void size_caps(Plan *pl) {
+    const int64_t per = pl->total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
+    pl->cap_nodes = std::max<int64_t>(pl->n_inst, 6 * per) + 16;
+    pl->cap_rot = pl->cap_nodes + 20 * per + 16;
+    pl->cap_leaves = pl->n_inst + 6 * (int64_t)pl->max_levels * per + 16;
+    pl->cap_tiles = pl->total / pl->tile + (pl->cells ? 2 : 1) * pl->cap_leaves + 16;
+    pl->leaf_shift = leaf_shift(*pl);
+}
+
 // Sizes and derived limits of one pipeline run.
 bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int64_t max_inst,
                int cfg, Plan *pl) {
@@ -297,16 +325,7 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->leaf_span = (tiles_per_leaf > 2 ? tiles_per_leaf - 2 : 0) * pl->tile;
     pl->grid_leaf = G;
     if (max_inst <= 0 || max_inst > total) max_inst = total;
-    // Division levels: children are at most 9/16 of the parent (plus one for
-    // rounding); a node of at most max(leaf_cap, 2*leaf_span) elements is a
-    // leaf; the last level only classifies.
-    const double stop = (double)std::max<int64_t>(pl->leaf_cap, 2 * pl->leaf_span);
-    int lv = 1;
-    double sz = (double)max_inst;
-    while (sz > stop && lv < kMaxLevels) {
-        sz = sz * 9.0 / 16.0 + 1.0;
-        ++lv;
-    }
+    const int lv = division_levels(*pl, max_inst);
     pl->max_levels = lv;
     pl->split_method = kSplitCorank;
     pl->rot_method = kRotSwapRev;
@@ -320,18 +339,25 @@ bool make_plan(DevState *ds, int ek, int ev, int64_t n_inst, int64_t total, int6
     pl->row_stride = 0;
     pl->rot_scale = 1;
     pl->sort_width = 0;
-    // A node is split only when it exceeds the leaf capacity, so a level has
-    // fewer than `per` split nodes; a level's node list takes children of
-    // the level before (2 per split) and grandchildren of fused nodes two
-    // levels before (4 per split); a fused node emits at most kMaxCuts/2
-    // cycles.
-    int64_t per = total / std::max<int64_t>(pl->leaf_cap, 1) + 1;
-    pl->cap_nodes = std::max<int64_t>(n_inst, 6 * per) + 16;
-    pl->cap_rot = pl->cap_nodes + 20 * per + 16;
-    pl->cap_leaves = n_inst + 6 * (int64_t)lv * per + 16;
-    pl->cap_tiles = total / pl->tile + pl->cap_leaves + 16;
-    pl->leaf_shift = leaf_shift(*pl);
+    pl->cells = 0;
+    size_caps(pl);
     return true;
+}
+
+// Cell-aligned tiles whose co-ranks are found beside the first division
+// level (im_split.hip, k_split), for a single instance of packed keys with
+// exact co-rank splits, whose leaves are then the stable merge's own output
+// ranges.  A leaf of S elements meets up to ceil(S/tile) + 1 cells, so the
+// size bound of a leaf drops by one tile to keep every leaf within the
+// read-ahead of the leaf merge; the tile bound grows by one per leaf.
+// (Called for a single instance only: its size is the plan's total.)
+void set_cells(Plan &pl, bool eligible) {
+    pl.cells = (eligible && pl.leaf_cap >= 3 * pl.tile) ? 1 : 0;
+    if (pl.cells) {
+        pl.leaf_cap -= pl.tile;
+        pl.max_levels = division_levels(pl, pl.total);
+        size_caps(&pl);
+    }
 }
 
 // Rows of row_bytes bytes moved in chunks of ch bytes (row_bytes % ch == 0).
@@ -408,6 +434,7 @@ size_t carve(const Plan &pl, int64_t flag_slots, void *base, Work *w) {
     x.tile_rank = (int64_t *)take(sizeof(int64_t) * pl.cap_tiles);
     x.tile_leaf = (int32_t *)take(sizeof(int32_t) * pl.cap_tiles);
     x.tile_geo = (TileGeo *)take(sizeof(TileGeo) * pl.cap_tiles);
+    x.cell_rank = pl.cells ? (int64_t *)take(sizeof(int64_t) * (pl.total / pl.tile + 2)) : nullptr;
     x.offsets1 = (int64_t *)take(sizeof(int64_t) * 4);
     x.cs_stash_k = nullptr;
     x.cs_stash_v = nullptr;
@@ -555,9 +582,10 @@ int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *
         prof_end(e1, kStRotate, 2, s);
     }
     hipEvent_t e3 = prof ? prof_begin(s) : nullptr;
-    IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
+    if (!pl.cells)
+        IM_HIP(launch_tilerank(key_dt, keys, offs, pl, w, mlp, s), "launch tile co-rank");
     IM_HIP(launch_tiledeps(pl, w, s), "launch tile dependencies");
-    prof_end(e3, kStTileRank, 2, s);
+    prof_end(e3, kStTileRank, pl.cells ? 1 : 2, s);
     return IM_OK;
 }
 
@@ -610,12 +638,14 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         if (!make_plan(ds, ek, ev, n_inst, total, max_inst, cfg, &pl))
             return fail(IM_ERR_HIP, "could not size the leaf merge grid (occupancy query failed)");
     }
-    if (pl.leaf_shift == 0)
-        return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");
     pl.split_method = split_method;
     pl.rot_method = rot_method;
     pl.sort_width = sort_width;
     if (split_method != kSplitCorank || rot_method != kRotSwapRev) pl.fuse = 0;   // the paper's modes as such
+    set_cells(pl, n_inst == 1 && rows.bytes == 0 && mlp == nullptr && sort_width == 0 &&
+                      split_method == kSplitCorank);
+    if (pl.leaf_shift == 0)
+        return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");
     int64_t &flag_cap = static_scratch ? ds->scr_flag_cap : ds->flag_cap;
     uint32_t &epoch = static_scratch ? ds->scr_epoch : ds->epoch;
     size_t need = carve(pl, flag_cap, nullptr, nullptr);
@@ -972,6 +1002,10 @@ size_t inplace_merge_workspace_bytes_batched(int64_t total_elems, int64_t n_inst
                            std::max<int64_t>(total_elems, 1), 0, cfg, &pl))
                 return 0;
             need = std::max(need, carve(pl, 0, nullptr, nullptr));
+            if (n_inst <= 1) {           // a single pair may run with cell tiles
+                set_cells(pl, true);
+                need = std::max(need, carve(pl, 0, nullptr, nullptr));
+            }
         }
     }
     return need;

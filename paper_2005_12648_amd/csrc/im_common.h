@@ -130,6 +130,12 @@ struct Plan {
     int32_t rot_method;     // kRotSwapRev or kRotCS
     int64_t cap_stash;      // circular shifting: stash slots per level
     int32_t fuse;           // fuse two division levels into one exchange where possible
+    // Leaf tiles are the cells [m*tile, (m+1)*tile) of the instance's output
+    // cut at leaf boundaries, and the co-ranks of the cell boundaries are
+    // found on the input layout, beside the first division level (single
+    // instance, exact co-rank splits): no tile search after the division.
+    // 0: tiles of `tile` outputs from each leaf's start, searched after it.
+    int32_t cells;
     int32_t leaf_shift;     // bits of the tile count in the packed leaf/tile counter
                             // (0: the caps do not fit in 64 bits; the plan is refused)
     // Rows (elements of several words ordered by their leading key): the
@@ -179,6 +185,7 @@ struct Work {
     int64_t *tile_start;     // per leaf: first tile index (exclusive scan)
     int64_t *tile_rank;      // per tile: co-rank at the tile's first diagonal
     int32_t *tile_leaf;      // per tile: its leaf
+    int64_t *cell_rank;      // Plan::cells: co-rank at each cell boundary m*tile (m = 0..cells)
     TileGeo *tile_geo;       // per slot: the tile's geometry and readers
     unsigned int *tile_flag; // per tile: == epoch once its inputs are in LDS
     int64_t *offsets1;       // [3] offsets of a single-instance call

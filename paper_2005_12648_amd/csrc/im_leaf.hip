@@ -3,8 +3,11 @@
 // After the division (Sec. 3; Alg. 3), each leaf is a contiguous pair
 // A_p | B_p whose merged output occupies exactly the leaf's own region, so
 // leaves are independent (the per-pair merge of Alg. 2/3).  A leaf is cut
-// into tiles of `tile` output elements; the co-rank of every tile diagonal
-// inside its leaf is known (k_tilerank).  One workgroup merges one tile:
+// into tiles of `tile` output elements (for a single instance: the cells of
+// `tile` outputs of the whole output that the leaf meets); the co-rank of
+// every tile diagonal inside its leaf is known (k_tilerank, or the cell
+// co-ranks found before the division moves data).  One workgroup merges one
+// tile:
 //   1. load its A-slice and B-slice into LDS (coalesced, contiguous);
 //   2. every thread finds its own sub-diagonal by a co-rank search in LDS and
 //      merges `ipt` outputs into registers (stable: ties take A);
@@ -984,12 +987,13 @@ hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int6
 }
 
 // Readers of each tile's window.  Tile i of a leaf (parts la, lb, size S)
-// writes [iT, min((i+1)T, S)).  The A elements there, [pa0, pa1) =
-// [iT, min((i+1)T, la)), are read by the tiles j whose A-slice
-// [ia(j), ia(j+1)) meets that range: from the first j with ia(j+1) > pa0 to
-// the last j with ia(j) < pa1.  The B elements there, B indices
-// [pb0, pb1) = [max(iT, la) - la, min((i+1)T, S) - la), are read by the tiles
-// whose B-slice [jb(j), jb(j+1)) meets it, jb(j) = min(jT, S) - ia(j): from
+// writes [c_i, c_{i+1}): c_i = iT, or with Plan::cells the boundaries of the
+// instance's cells of T outputs inside the leaf (c_0 = 0, c_nt = S).  The A
+// elements there, [pa0, pa1) = [c_i, min(c_{i+1}, la)), are read by the
+// tiles j whose A-slice [ia(j), ia(j+1)) meets that range: from the first j
+// with ia(j+1) > pa0 to the last j with ia(j) < pa1.  The B elements there,
+// B indices [pb0, pb1) = [max(c_i, la) - la, c_{i+1} - la), are read by the
+// tiles whose B-slice [jb(j), jb(j+1)) meets it, jb(j) = c_j - ia(j): from
 // the first j with jb(j+1) > pb0 to the last j with jb(j) < pb1.  An empty
 // range is stored as [0, -1].  (Every tile between the window and its last
 // reader used to be polled as well: hundreds of device-scope flag loads per
@@ -1000,25 +1004,56 @@ hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int6
 __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
     int64_t ntiles = (int64_t)w.ctr->tiles;
     if (ntiles > pl.cap_tiles) ntiles = pl.cap_tiles;
+    int64_t nleaves = (int64_t)w.ctr->leaves;
+    if (nleaves > pl.cap_leaves) nleaves = pl.cap_leaves;
     const int64_t T = pl.tile;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t l = w.tile_leaf[t];
+        int64_t l;
+        if (pl.cells) {
+            // leaf = last l with tile_start[l] <= t (no tile search ran)
+            int64_t lo = 0, hi = nleaves;
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (w.tile_start[mid] <= t) lo = mid; else hi = mid;
+            }
+            l = lo;
+        } else {
+            l = w.tile_leaf[t];
+        }
         const Leaf lf = w.leaves[l];
         const int64_t ts = w.tile_start[l];
         const int64_t nt = lf.ntiles;
         const int64_t i = t - ts;
         const int64_t S = lf.la + lf.lb;
+        // Leaf-local output start of tile j (j = nt: the leaf's end): j*T, or
+        // with cells the boundary of the instance's cell m0 + j.
+        const int64_t m0 = pl.cells ? lf.k0 / T : 0;
+        auto cstart = [&](int64_t j) -> int64_t {
+            if (j >= nt) return S;
+            if (j == 0) return 0;
+            return pl.cells ? (m0 + j) * T - lf.k0 : j * T;
+        };
+        // Co-rank at tile j's start; a cell co-rank is clamped to the range a
+        // co-rank can take there, which only unsorted runs ever leave.
+        auto ia = [&](int64_t j) -> int64_t {
+            if (j >= nt) return lf.la;
+            if (!pl.cells) return w.tile_rank[ts + j];
+            if (j == 0) return 0;
+            const int64_t d = cstart(j);
+            const int64_t v = w.cell_rank[m0 + j] - lf.i0;
+            const int64_t vlo = d - lf.lb > 0 ? d - lf.lb : 0;
+            const int64_t vhi = d < lf.la ? d : lf.la;
+            return v < vlo ? vlo : (v > vhi ? vhi : v);
+        };
+        auto jb = [&](int64_t j) -> int64_t { return cstart(j) - ia(j); };
+        const int64_t d0 = cstart(i);
+        const int64_t d1 = cstart(i + 1);
         int64_t alo = 0, ahi = -1, blo = 0, bhi = -1;
         if (nt > 1) {
-            auto ia = [&](int64_t j) -> int64_t { return j < nt ? w.tile_rank[ts + j] : lf.la; };
-            auto jb = [&](int64_t j) -> int64_t {
-                int64_t d = j * T < S ? j * T : S;
-                return d - ia(j);
-            };
-            const int64_t pa0 = i * T;
-            const int64_t pa1 = (i + 1) * T < lf.la ? (i + 1) * T : lf.la;
-            const int64_t e = (i + 1) * T < S ? (i + 1) * T : S;
+            const int64_t pa0 = d0;
+            const int64_t pa1 = d1 < lf.la ? d1 : lf.la;
+            const int64_t e = d1;
             const int64_t pb0 = (pa0 > lf.la ? pa0 : lf.la) - lf.la;
             const int64_t pb1 = e - lf.la;
             const bool has_a = pa0 < lf.la;          // window holds A elements
@@ -1033,11 +1068,11 @@ __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
             int64_t lo0 = 0, hi0 = has_a ? nt - 1 : 0, lo1 = 0, hi1 = hi0;
             int64_t lo2 = 0, hi2 = has_b ? nt - 1 : 0, lo3 = 0, hi3 = hi2;
             while (lo0 < hi0 || lo1 < hi1 || lo2 < hi2 || lo3 < hi3) {
-                const int64_t m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1 + 1) >> 1;
+                const int64_t m0_ = (lo0 + hi0) >> 1, m1 = (lo1 + hi1 + 1) >> 1;
                 const int64_t m2 = (lo2 + hi2) >> 1, m3 = (lo3 + hi3 + 1) >> 1;
                 // every index is in [0, nt]; ia(nt) needs no load
-                const int64_t v0 = ia(m0 + 1), v1 = ia(m1), v2 = jb(m2 + 1), v3 = jb(m3);
-                if (lo0 < hi0) { if (v0 > pa0) hi0 = m0; else lo0 = m0 + 1; }
+                const int64_t v0 = ia(m0_ + 1), v1 = ia(m1), v2 = jb(m2 + 1), v3 = jb(m3);
+                if (lo0 < hi0) { if (v0 > pa0) hi0 = m0_; else lo0 = m0_ + 1; }
                 if (lo1 < hi1) { if (v1 < pa1) lo1 = m1; else hi1 = m1 - 1; }
                 if (lo2 < hi2) { if (v2 > pb0) hi2 = m2; else lo2 = m2 + 1; }
                 if (lo3 < hi3) { if (v3 < pb1) lo3 = m3; else hi3 = m3 - 1; }
@@ -1047,11 +1082,9 @@ __global__ __launch_bounds__(256) void k_tiledeps(Plan pl, Work w) {
         }
         // the record of the slot that processes tile t (a dir-1 leaf takes
         // its tiles in decreasing order)
-        const int64_t d0 = i * T;
-        const int64_t d1 = d0 + T < S ? d0 + T : S;
         const int64_t n = d1 - d0;
-        const int64_t ia0 = w.tile_rank[t];
-        const int64_t ia1 = i + 1 < nt ? w.tile_rank[t + 1] : lf.la;
+        const int64_t ia0 = ia(i);
+        const int64_t ia1 = ia(i + 1);
         // For ascending runs na = ia1 - ia0 already lies in this interval; the
         // clamp only keeps every access inside the leaf when a caller passes
         // unsorted runs (then the result is an unspecified permutation).

@@ -140,7 +140,12 @@ __device__ __forceinline__ void emit_rot(const Plan &pl, const Work &w, int leve
 // over the leaves after the division.
 __device__ __forceinline__ void emit_leaf(const Plan &pl, const Work &w, const Node &nd) {
     const int64_t S = nd.la + nd.lb;
-    const unsigned long long nt = (unsigned long long)((S + pl.tile - 1) / pl.tile);
+    // tiles of `tile` outputs from the leaf's start, or the instance's cells
+    // that the leaf meets (its first and last may be partial)
+    const unsigned long long nt =
+        pl.cells ? (S > 0 ? (unsigned long long)((nd.k0 + S - 1) / pl.tile - nd.k0 / pl.tile + 1)
+                          : 0ull)
+                 : (unsigned long long)((S + pl.tile - 1) / pl.tile);
     const int sh = pl.leaf_shift;
     const unsigned long long packed = atomicAdd(&w.ctr->leaf_tiles, (1ull << sh) + nt);
     const unsigned long long slot = packed >> sh;
@@ -409,6 +414,43 @@ __device__ __forceinline__ int child_kind(const Plan &pl, int64_t la, int64_t lb
     return (mx * 16 <= S * 9) ? 1 : 2;
 }
 
+// Co-ranks of the cell boundaries m*tile (m = 0..cells) of a single
+// instance, on the layout before any exchange, one lane per boundary.  They
+// run in the first division level's launch (workgroups past the split's
+// own), beside its latency-bound searches.  The merge's leaves are ranges of
+// the stable merge's output, so a cell boundary inside a leaf that starts at
+// output k0 and A index i0 has the leaf-local co-rank cell_rank - i0 there.
+// Nothing is searched when the input is already in order (no leaf then).
+template <typename KP>
+__device__ void cell_coranks(KP data, const int64_t *__restrict__ offsets, const Plan &pl,
+                             const Work &w, int64_t b, int64_t nb) {
+    const int64_t o0 = offsets[0], o1 = offsets[1], o2 = offsets[2];
+    const int64_t la = o1 - o0, lb = o2 - o1;
+    if (la <= 0 || lb <= 0) return;
+    const KP A = data + o0;
+    const KP B = A + la;
+    if (A[la - 1] <= B[0]) return;
+    const int64_t S = la + lb;
+    const int64_t ncell = (S + pl.tile - 1) / pl.tile;
+    uint32_t probes = 0, searches = 0;
+    for (int64_t m = b * blockDim.x + threadIdx.x; m <= ncell; m += nb * blockDim.x) {
+        int64_t i;
+        if (m == 0) {
+            i = 0;
+        } else if (m == ncell) {
+            i = la;
+        } else {
+            ++searches;
+            i = corank_plain(A, la, B, lb, m * pl.tile, probes);
+        }
+        w.cell_rank[m] = i;
+    }
+    if (searches) {
+        atomicAdd(&w.ctr->searches, (unsigned long long)searches);
+        atomicAdd(&w.ctr->probes, (unsigned long long)probes);
+    }
+}
+
 // One lane per node classifies it (early exits, leaf); the nodes of a wave
 // that must be split are then searched one after another by the whole wave
 // with the cooperative 64-ary co-rank (a handful of dependent rounds).  A
@@ -419,7 +461,13 @@ template <typename K, typename KP, bool LEARNED>
 __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
                                                          const int64_t *__restrict__ offsets,
                                                          Plan pl, Work w, int level,
-                                                         const MlpDev *__restrict__ mlp) {
+                                                         const MlpDev *__restrict__ mlp,
+                                                         int split_grid) {
+    if ((int)blockIdx.x >= split_grid) {      // cell co-ranks (first level, Plan::cells)
+        cell_coranks(data, offsets, pl, w, (int64_t)blockIdx.x - split_grid,
+                     (int64_t)gridDim.x - split_grid);
+        return;
+    }
     const unsigned long long cnt_raw = w.ctr->level_nodes[level];
     const int64_t cnt = (int64_t)cnt_raw < pl.cap_nodes ? (int64_t)cnt_raw : pl.cap_nodes;
     const Node *in = w.nodes[level % 3];
@@ -430,7 +478,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
     const bool may_fuse = pl.fuse && level + 2 <= pl.max_levels - 1;
     const int lane = threadIdx.x & 63;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = (int64_t)split_grid * blockDim.x;
     if (gid == 0 && cnt > 0) atomicMax(&w.ctr->levels_used, (unsigned long long)(level + 1));
     uint32_t rounds = 0, searches = 0;          // wave-uniform counts
     uint32_t fm_probes = 0, fm_searches = 0;    // per lane (FindMedian)
@@ -796,16 +844,20 @@ static hipError_t split_t(const void *data, const int64_t *offs, const Plan &pl,
     const int th = few ? 64 : kSplitThreads;
     const int g = few ? (int)(pl.cap_nodes < 2048 ? pl.cap_nodes : 2048)
                       : grid_for(pl.cap_nodes, th, 2048);
+    // the first level of a cell-tiled merge also finds the cell co-ranks:
+    // one lane per cell boundary in workgroups past the split's
+    const int gc = (pl.cells && level == 0) ? (int)((pl.total / pl.tile + 2 + th - 1) / th) : 0;
     if (pl.row_stride > 0) {
-        if (mlp) return hipErrorInvalidValue;
+        if (mlp || gc) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_split<K, RowKeys<K>, false>), dim3(g), dim3(th), 0, s,
-                           RowKeys<K>{(const K *)data, pl.row_stride}, offs, pl, w, level, mlp);
+                           RowKeys<K>{(const K *)data, pl.row_stride}, offs, pl, w, level, mlp, g);
     } else if (mlp) {
+        if (gc) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_split<K, const K *, true>), dim3(g), dim3(th), 0, s,
-                           (const K *)data, offs, pl, w, level, mlp);
+                           (const K *)data, offs, pl, w, level, mlp, g);
     } else {
-        hipLaunchKernelGGL((k_split<K, const K *, false>), dim3(g), dim3(th), 0, s,
-                           (const K *)data, offs, pl, w, level, mlp);
+        hipLaunchKernelGGL((k_split<K, const K *, false>), dim3(g + gc), dim3(th), 0, s,
+                           (const K *)data, offs, pl, w, level, mlp, g);
     }
     return hipGetLastError();
 }
