@@ -208,12 +208,20 @@ __device__ __forceinline__ void publish_read(const TileGeo &g, const Plan &pl, c
 }
 
 // Pieces of the leaf-merge pipeline for one workgroup.
-template <typename K, typename V, int THREADS, int IPT>
+// WIDE: 16-byte groups in the transpose and the stores where the element
+// allows it (off for the depth-4 pipeline, whose three register sets leave
+// no room for the aligned register quads those accesses need).
+template <typename K, typename V, int THREADS, int IPT, bool WIDE = true>
 struct LeafOps {
     static constexpr int T = THREADS * IPT;
     static constexpr bool HAS_V = !std::is_same<V, NoValL>::value;
     static constexpr int PE = LdsPad<T, IPT>::elems;
     static constexpr int VN = HAS_V ? IPT : 1;
+    // 4-byte keys alone leave the merge in 16-byte groups (VQ per thread, VR
+    // outputs left over) and are stored 16 bytes at a time
+    static constexpr bool VEC = WIDE && sizeof(K) == 4 && !HAS_V && IPT >= 4;
+    static constexpr int VQ = IPT / 4;
+    static constexpr int VR = IPT % 4;
 
     // Load the tile's slices into LDS and publish "inputs read".
     static __device__ __forceinline__ void stage(const K *keys, const V *vals, const TileGeo &g,
@@ -300,12 +308,39 @@ struct LeafOps {
         __syncthreads();
         int xb = tid;
         asm volatile("" : "+v"(xb));
+        if constexpr (VEC) {
+            // 16-byte groups: thread p takes outputs 4p + u*4*THREADS .. +3
+            // (one 16-byte LDS read each), then the IPT mod 4 outputs left
+            // over one by one (striped).  Reads past n stay in the tile's
+            // LDS and are never stored.
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int u = 0; u < IPT; ++u) {
-            const int x = xb + u * THREADS;
-            if (x < n) {
-                out[u] = sk[x];
-                if constexpr (HAS_V) vout[u] = sv[x];
+            for (int u = 0; u < VQ; ++u) {
+                const int x = 4 * xb + u * 4 * THREADS;
+                const u32x4 v = *reinterpret_cast<const u32x4 *>(sk + x);
+                // take the four words out of the register quad one by one,
+                // so that the held outputs need no aligned quads (with three
+                // register sets live that would spill)
+                uint32_t w0 = v.x, w1 = v.y, w2 = v.z, w3 = v.w;
+                asm volatile("" : "+v"(w0), "+v"(w1), "+v"(w2), "+v"(w3));
+                out[4 * u] = __builtin_bit_cast(K, w0);
+                out[4 * u + 1] = __builtin_bit_cast(K, w1);
+                out[4 * u + 2] = __builtin_bit_cast(K, w2);
+                out[4 * u + 3] = __builtin_bit_cast(K, w3);
+            }
+#pragma unroll
+            for (int r = 0; r < VR; ++r) {
+                const int x = VQ * 4 * THREADS + xb + r * THREADS;
+                if (x < n) out[4 * VQ + r] = sk[x];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < IPT; ++u) {
+                const int x = xb + u * THREADS;
+                if (x < n) {
+                    out[u] = sk[x];
+                    if constexpr (HAS_V) vout[u] = sv[x];
+                }
             }
         }
         before_last_sync();
@@ -317,13 +352,45 @@ struct LeafOps {
         return wait_window<THREADS>(g, pl, w);
     }
 
-    // Coalesced store of the window from registers.
+    // Coalesced store of the window from registers (16-byte stores where the
+    // outputs were taken in 16-byte groups: a wave writes 1 KB per store).
     static __device__ __forceinline__ void store(K *keys, V *vals, const TileGeo &g,
                                                  const K (&out)[IPT], const V (&vout)[VN]) {
         const int n = g.n;
         int xb = threadIdx.x;
         asm volatile("" : "+v"(xb));
         const __amdgpu_buffer_rsrc_t ro = buf_rsrc(keys + g.out0, (int64_t)n * sizeof(K));
+        if constexpr (VEC) {
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+            for (int u = 0; u < VQ; ++u) {
+                const int x = 4 * xb + u * 4 * THREADS;
+                if (x + 3 < n) {
+                    // (copied into a fresh quad, as at the LDS read)
+                    uint32_t w0 = __builtin_bit_cast(uint32_t, out[4 * u]);
+                    uint32_t w1 = __builtin_bit_cast(uint32_t, out[4 * u + 1]);
+                    uint32_t w2 = __builtin_bit_cast(uint32_t, out[4 * u + 2]);
+                    uint32_t w3 = __builtin_bit_cast(uint32_t, out[4 * u + 3]);
+                    asm volatile("" : "+v"(w0), "+v"(w1), "+v"(w2), "+v"(w3));
+                    u32x4 v;
+                    v.x = w0;
+                    v.y = w1;
+                    v.z = w2;
+                    v.w = w3;
+                    __builtin_amdgcn_raw_buffer_store_b128(v, ro, x * 4, 0, kStoreNT);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (x + k < n) buf_store<K>(out[4 * u + k], ro, (x + k) * 4);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < VR; ++r) {
+                const int x = VQ * 4 * THREADS + xb + r * THREADS;
+                if (x < n) buf_store<K>(out[4 * VQ + r], ro, x * 4);
+            }
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
             const int x = xb + u * THREADS;
@@ -415,7 +482,7 @@ __device__ __forceinline__ bool leaf_step4(K *keys, V *vals, K *sk, V *sv, const
                                            unsigned long long &pend,
                                            K (&cur)[IPT], V (&vcur)[LeafOps<K, V, THREADS, IPT>::VN],
                                            K (&nxt)[IPT], V (&vnxt)[LeafOps<K, V, THREADS, IPT>::VN]) {
-    using Ops = LeafOps<K, V, THREADS, IPT>;
+    using Ops = LeafOps<K, V, THREADS, IPT, false>;
     int64_t t2 = p.ntiles;
     if (p.has1) {
         Ops::template merge<true>(p.g1, sk, sv, nxt, vnxt, [&] {
@@ -459,7 +526,7 @@ __device__ __forceinline__ bool leaf_step4(K *keys, V *vals, K *sk, V *sv, const
 template <typename K, typename V, int THREADS, int IPT, int DEPTH>
 __global__ __launch_bounds__(THREADS, 4) void k_leafmerge(K *__restrict__ keys, V *__restrict__ vals,
                                                           Plan pl, Work w) {
-    using Ops = LeafOps<K, V, THREADS, IPT>;
+    using Ops = LeafOps<K, V, THREADS, IPT, (DEPTH < 4)>;
     static_assert(DEPTH >= 2 && DEPTH <= 4, "pipeline depth");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_slot[1];
