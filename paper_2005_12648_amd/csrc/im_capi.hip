@@ -642,7 +642,7 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     pl.rot_method = rot_method;
     pl.sort_width = sort_width;
     if (split_method != kSplitCorank || rot_method != kRotSwapRev) pl.fuse = 0;   // the paper's modes as such
-    set_cells(pl, n_inst == 1 && rows.bytes == 0 && mlp == nullptr && sort_width == 0 &&
+    set_cells(pl, n_inst == 1 && rows.bytes == 0 && sort_width == 0 &&
                       split_method == kSplitCorank);
     if (pl.leaf_shift == 0)
         return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");

@@ -133,7 +133,8 @@ struct Plan {
     // Leaf tiles are the cells [m*tile, (m+1)*tile) of the instance's output
     // cut at leaf boundaries, and the co-ranks of the cell boundaries are
     // found on the input layout, beside the first division level (single
-    // instance, exact co-rank splits): no tile search after the division.
+    // instance, exact co-rank splits, plain or learned searches): no tile
+    // search after the division.
     // 0: tiles of `tile` outputs from each leaf's start, searched after it.
     int32_t cells;
     int32_t leaf_shift;     // bits of the tile count in the packed leaf/tile counter

@@ -421,9 +421,12 @@ __device__ __forceinline__ int child_kind(const Plan &pl, int64_t la, int64_t lb
 // the stable merge's output, so a cell boundary inside a leaf that starts at
 // output k0 and A index i0 has the leaf-local co-rank cell_rank - i0 there.
 // Nothing is searched when the input is already in order (no leaf then).
-template <typename KP>
+// With a merge model each search starts from the model's bracket (the
+// learned split: fewer probes, so fewer lines fetched in this launch).
+template <bool LEARNED, typename KP>
 __device__ void cell_coranks(KP data, const int64_t *__restrict__ offsets, const Plan &pl,
-                             const Work &w, int64_t b, int64_t nb) {
+                             const Work &w, const MlpDev *__restrict__ mlp, int64_t b,
+                             int64_t nb) {
     const int64_t o0 = offsets[0], o1 = offsets[1], o2 = offsets[2];
     const int64_t la = o1 - o0, lb = o2 - o1;
     if (la <= 0 || lb <= 0) return;
@@ -441,7 +444,11 @@ __device__ void cell_coranks(KP data, const int64_t *__restrict__ offsets, const
             i = la;
         } else {
             ++searches;
-            i = corank_plain(A, la, B, lb, m * pl.tile, probes);
+            const int64_t d = m * pl.tile;
+            if (LEARNED)
+                i = corank_learned(A, la, B, lb, d, mlp, d, S, la, 0, probes);
+            else
+                i = corank_plain(A, la, B, lb, d, probes);
         }
         w.cell_rank[m] = i;
     }
@@ -464,8 +471,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(KP data,
                                                          const MlpDev *__restrict__ mlp,
                                                          int split_grid) {
     if ((int)blockIdx.x >= split_grid) {      // cell co-ranks (first level, Plan::cells)
-        cell_coranks(data, offsets, pl, w, (int64_t)blockIdx.x - split_grid,
-                     (int64_t)gridDim.x - split_grid);
+        cell_coranks<LEARNED>(data, offsets, pl, w, mlp, (int64_t)blockIdx.x - split_grid,
+                              (int64_t)gridDim.x - split_grid);
         return;
     }
     const unsigned long long cnt_raw = w.ctr->level_nodes[level];
@@ -852,8 +859,7 @@ static hipError_t split_t(const void *data, const int64_t *offs, const Plan &pl,
         hipLaunchKernelGGL((k_split<K, RowKeys<K>, false>), dim3(g), dim3(th), 0, s,
                            RowKeys<K>{(const K *)data, pl.row_stride}, offs, pl, w, level, mlp, g);
     } else if (mlp) {
-        if (gc) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_split<K, const K *, true>), dim3(g), dim3(th), 0, s,
+        hipLaunchKernelGGL((k_split<K, const K *, true>), dim3(g + gc), dim3(th), 0, s,
                            (const K *)data, offs, pl, w, level, mlp, g);
     } else {
         hipLaunchKernelGGL((k_split<K, const K *, false>), dim3(g + gc), dim3(th), 0, s,
