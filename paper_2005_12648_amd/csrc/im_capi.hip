@@ -571,6 +571,11 @@ int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *
         if (bits & kErrOffsets) return fail(IM_ERR_INVALID_ARG, "offsets are not monotone");
         if (bits & kErrNotSorted) return fail(IM_ERR_NOT_SORTED, "an input run is not ascending");
     }
+    // A single pair with L_A == L_B splits at the symmetric diagonal (or is
+    // one exchange of two equal parts): the first level has block swaps or
+    // cycles only, never the second pass of three reversals.
+    const bool equal_root = n_inst == 1 && d_offsets == nullptr && la == lb &&
+                            pl.split_method == kSplitCorank && pl.rot_method == kRotSwapRev;
     for (int lv = 0; lv < pl.max_levels; ++lv) {
         hipEvent_t e0 = prof ? prof_begin(s) : nullptr;
         IM_HIP(launch_split(key_dt, keys, offs, pl, w, lv, mlp, s), "launch split");
@@ -578,8 +583,10 @@ int enqueue_division(int key_dt, int ev, void *keys, void *vals, const int64_t *
         if (lv + 1 == pl.max_levels) break;   // the last level only classifies
         hipEvent_t e1 = prof ? prof_begin(s) : nullptr;
         IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 0, s), "launch rotate A");
-        IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");
-        prof_end(e1, kStRotate, 2, s);
+        const bool phase_b = !(lv == 0 && equal_root);
+        if (phase_b)
+            IM_HIP(launch_rotate(ek, ev, keys, vals, pl, w, lv, 1, s), "launch rotate B");
+        prof_end(e1, kStRotate, phase_b ? 2 : 1, s);
     }
     hipEvent_t e3 = prof ? prof_begin(s) : nullptr;
     if (!pl.cells)
