@@ -583,7 +583,7 @@ def bench_rows(torch, im, oracle, gen, dev, steps):
     (the floor of any method that moves every row once) and the oracle."""
     out = {}
     total = 2 ** 30
-    for W in (64, 256, 1024, 4096, 16384, 65536):
+    for W in (64, 256, 1024, 4096, 16384, 65536, 65540):
         n = total // W
         la = n // 2
         log("f4: rows of %d bytes, %d + %d" % (W, la, n - la))
@@ -608,8 +608,8 @@ def bench_rows(torch, im, oracle, gen, dev, steps):
         moved = 2 * W * (st["rotated_elems"] + st["leaf_elems"])     # read + write
         out["rows_%d_B" % W] = {
             "rows": n, "ms": round(ms, 4), "grows_s": round(n / ms / 1e6, 4),
-            "effective_gb_s": round(2 * total / ms / 1e6, 1),
-            "copy_ms": round(copy_ms, 4), "copy_gb_s": round(2 * total / copy_ms / 1e6, 1),
+            "effective_gb_s": round(2 * n * W / ms / 1e6, 1),
+            "copy_ms": round(copy_ms, 4), "copy_gb_s": round(2 * n * W / copy_ms / 1e6, 1),
             "moved_bytes": moved, "moved_gb_s": round(moved / ms / 1e6, 1),
             "levels_used": st["levels_used"], "leaves": st["leaves"],
             "fused_nodes": st["fused_nodes"], "tile_rows": st["tile"],
@@ -618,8 +618,9 @@ def bench_rows(torch, im, oracle, gen, dev, steps):
             "mismatched_rows": bad}
         del pristine, buf
         torch.cuda.empty_cache()
-    return {"workload": "rows of W bytes (int32 key + payload), 2^30/W rows, L_A = L_B, "
-                        "keys uniform in [0,2^31)", "widths": out}
+    return {"workload": "rows of W bytes (int32 key + payload), floor(2^30/W) rows, "
+                        "L_A = L_B (rounded down), keys uniform in [0,2^31); 65540 B is "
+                        "the paper's largest element", "widths": out}
 
 
 def main():

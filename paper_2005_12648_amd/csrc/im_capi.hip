@@ -97,7 +97,7 @@ struct DevState {
     hipEvent_t done = nullptr;   // last enqueued use of the workspace
     bool done_valid = false;
     int grid[kLeafCfgs][2][3] = {};   // leaf grid by (config, key 4/8, payload 0/4/8)
-    int rows_grid[4][3] = {};         // rows leaf grid by (key code, chunk 4/8/16)
+    int rows_grid[4][4] = {};         // rows leaf grid by (key code, row kind)
     // Autotuned leaf configuration by (key 4/8, payload 0/4/8, floor(log2 of
     // the mean instance size)); -1: not tuned.
     int tuned[2][3][64];
@@ -360,27 +360,27 @@ void set_cells(Plan &pl, bool eligible) {
     }
 }
 
-// Rows of row_bytes bytes moved in chunks of ch bytes (row_bytes % ch == 0).
-int chunk_index(int ch) { return ch == 4 ? 0 : (ch == 8 ? 1 : 2); }
-
 // Plan of a rows merge: the same division (keys read row_bytes apart,
 // exchanges in 4-byte units), leaves merged by k_leafrows: tiles of R rows,
-// two tiles read ahead per workgroup, so a leaf may have 2G tiles.
-bool make_plan_rows(DevState *ds, int key_dt, int64_t row_bytes, int ch, int64_t total,
+// depth tiles held per workgroup (2 or 3 by row kind), so a leaf may have
+// depth x G tiles.
+bool make_plan_rows(DevState *ds, int key_dt, int64_t row_bytes, int kind, int64_t total,
                     Plan *pl) {
-    int &gc = ds->rows_grid[key_dt][chunk_index(ch)];
-    if (gc == 0) gc = rows_grid(key_dt, ch);
+    if (kind < 0 || kind >= rows_kinds()) return false;
+    int &gc = ds->rows_grid[key_dt][kind];
+    if (gc == 0) gc = rows_grid(key_dt, kind);
     int G = gc;
-    const int R = rows_tile(row_bytes, ch);
+    const int R = rows_tile(row_bytes, kind);
     if (G <= 0 || R < 1) return false;
     if (const char *g_env = std::getenv("IM_LEAF_GRID")) {
         long v = std::strtol(g_env, nullptr, 10);
         if (v >= 1 && v < G) G = (int)v;
     }
-    int64_t tiles_per_leaf = 2 * (int64_t)G;
+    const int64_t depth = rows_depth(kind);
+    int64_t tiles_per_leaf = depth * G;
     if (const char *cap_env = std::getenv("IM_LEAF_TILES")) {
         long v = std::strtol(cap_env, nullptr, 10);
-        if (v >= 1 && v <= 2 * (int64_t)G) tiles_per_leaf = v;
+        if (v >= 1 && v <= depth * G) tiles_per_leaf = v;
     }
     pl->cfg = 0;
     pl->n_inst = 1;
@@ -608,10 +608,10 @@ void record_stats(const Plan &pl, const Work &w) {
 
 // The whole merge: division levels, tile co-ranks, leaf merge.
 // cfg_override >= 0 forces a leaf configuration (autotuner).
-// Rows mode of run_pipeline: row bytes (0: packed keys) and chunk bytes.
+// Rows mode of run_pipeline: row bytes (0: packed keys) and row kind.
 struct RowsArg {
     int64_t bytes;
-    int ch;
+    int kind;
 };
 
 // sort_width > 0: a merge-sort pass over runs of that width (its offsets are
@@ -638,7 +638,7 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
     const int ek = key_size(key_dt);
     Plan pl = {};
     if (rows.bytes > 0) {
-        if (!make_plan_rows(ds, key_dt, rows.bytes, rows.ch, total, &pl))
+        if (!make_plan_rows(ds, key_dt, rows.bytes, rows.kind, total, &pl))
             return fail(IM_ERR_HIP, "could not size the rows leaf merge grid");
     } else {
         const int cfg = choose_cfg(ds, ek, ev, n_inst, total, cfg_override);
@@ -728,7 +728,7 @@ int run_pipeline(int key_dt, int ev, void *keys, void *vals, const int64_t *d_of
         if (rc) return rc;
         hipEvent_t e4 = prof ? prof_begin(s) : nullptr;
         if (rows.bytes > 0)
-            IM_HIP(launch_leafrows(key_dt, rows.ch, keys, rows.bytes, pl, w, s), "launch rows merge");
+            IM_HIP(launch_leafrows(key_dt, rows.kind, keys, rows.bytes, pl, w, s), "launch rows merge");
         else
             IM_HIP(launch_leafmerge(key_dt, ev, keys, vals, pl, w, s), "launch leaf merge");
         prof_end(e4, kStLeafMerge, 1, s);
@@ -848,27 +848,36 @@ int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B, int key_d
 
 // Rows: the largest chunk (16, 8 or 4 bytes) that divides the row and the
 // data address; 0 if the row shape is not supported.
-static int rows_chunk(const void *data, int64_t row_bytes, int key_dtype, const char **why) {
+// Row kind of a rows merge, -1 (with *why) if the rows cannot be merged:
+// the widest chunk that divides the row and the address and still puts a
+// whole row in a tile; of the 16-byte kinds, the one whose workgroup holds
+// more bytes of whole rows (depth x rows per tile x row bytes).
+static int rows_kind(const void *data, int64_t row_bytes, int key_dtype, const char **why) {
     const int kb = key_size(key_dtype);
     if (row_bytes < kb || row_bytes % kb != 0 || row_bytes % 4 != 0) {
         *why = "row bytes must be a positive multiple of the key size and of 4";
-        return 0;
+        return -1;
     }
     const uintptr_t a = (uintptr_t)data;
     if (a % (uintptr_t)kb != 0) {
         *why = "data must be aligned to the key size";
-        return 0;
+        return -1;
     }
-    // the widest chunk that divides the row and the address and still puts
-    // a whole row in a tile
-    int ch = 4;
-    if (row_bytes % 16 == 0 && a % 16 == 0 && rows_tile(row_bytes, 16) >= 1) ch = 16;
-    else if (row_bytes % 8 == 0 && a % 8 == 0 && rows_tile(row_bytes, 8) >= 1) ch = 8;
-    if (rows_tile(row_bytes, ch) < 1) {
-        *why = "row too large: at most 81920 bytes";
-        return 0;
+    int best = -1, best_ch = 0;
+    int64_t best_hold = 0;
+    for (int k = 0; k < rows_kinds(); ++k) {
+        const int ch = rows_chunk_bytes(k);
+        const int R = rows_tile(row_bytes, k);
+        if (R < 1 || row_bytes % ch != 0 || a % (uintptr_t)ch != 0) continue;
+        const int64_t hold = (int64_t)rows_depth(k) * R * row_bytes;
+        if (ch > best_ch || (ch == best_ch && hold > best_hold)) {
+            best = k;
+            best_ch = ch;
+            best_hold = hold;
+        }
     }
-    return ch;
+    if (best < 0) *why = "row too large: at most 81920 bytes";
+    return best;
 }
 
 int inplace_merge_rows(void *data, int64_t L_A, int64_t L_B, int64_t row_bytes, int key_dtype,
@@ -880,10 +889,10 @@ int inplace_merge_rows(void *data, int64_t L_A, int64_t L_B, int64_t row_bytes, 
         return fail(IM_ERR_INVALID_ARG, "array too large");
     if (L_A == 0 || L_B == 0) { g_err.clear(); return IM_OK; }
     const char *why = "";
-    const int ch = rows_chunk(data, row_bytes, key_dtype, &why);
-    if (ch == 0) return fail(IM_ERR_INVALID_ARG, why);
+    const int kind = rows_kind(data, row_bytes, key_dtype, &why);
+    if (kind < 0) return fail(IM_ERR_INVALID_ARG, why);
     return run_pipeline(key_dtype, 0, data, nullptr, nullptr, 1, L_A + L_B, L_A + L_B, L_A, L_B,
-                        nullptr, stream, -1, kSplitCorank, kRotSwapRev, RowsArg{row_bytes, ch});
+                        nullptr, stream, -1, kSplitCorank, kRotSwapRev, RowsArg{row_bytes, kind});
 }
 
 size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int key_dtype) {
@@ -892,10 +901,10 @@ size_t inplace_merge_rows_workspace_bytes(int64_t rows, int64_t row_bytes, int k
     if (!ds) return 0;
     std::lock_guard<std::mutex> lock(ds->mu);
     size_t need = 0;
-    for (int ch : {4, 8, 16}) {
-        if (row_bytes % ch != 0 || rows_tile(row_bytes, ch) < 1) continue;
+    for (int k = 0; k < rows_kinds(); ++k) {
+        if (row_bytes % rows_chunk_bytes(k) != 0 || rows_tile(row_bytes, k) < 1) continue;
         Plan pl = {};
-        if (!make_plan_rows(ds, key_dtype, row_bytes, ch, std::max<int64_t>(rows, 1), &pl))
+        if (!make_plan_rows(ds, key_dtype, row_bytes, k, std::max<int64_t>(rows, 1), &pl))
             return 0;
         need = std::max(need, carve(pl, 0, nullptr, nullptr));
     }

@@ -264,11 +264,16 @@ hipError_t launch_merge_oop(int key, const void *in, void *out, int64_t la, int6
 // apart: 1 for packed keys, the row length for rows).
 hipError_t launch_check_sorted(int key, const void *data, const int64_t *d_offsets,
                                int64_t n_inst, Counters *ctr, int64_t stride, hipStream_t s);
-// Wide rows (im_leaf.hip): rows per tile for (row bytes, chunk bytes), the
-// resident grid of the rows leaf merge, and its cooperative launch.
-int rows_tile(int64_t row_bytes, int ch);
-int rows_grid(int key, int ch);
-hipError_t launch_leafrows(int key, int ch, void *data, int64_t row_bytes, const Plan &pl,
+// Wide rows (im_leaf.hip).  A row kind 0 .. rows_kinds()-1 fixes the chunk
+// bytes rows move in, the chunks a thread holds and the tiles a workgroup
+// holds; for each: rows per tile for a row size (0: a row does not fit),
+// the resident grid of the rows leaf merge, and its cooperative launch.
+int rows_kinds();
+int rows_chunk_bytes(int kind);
+int rows_tile(int64_t row_bytes, int kind);
+int rows_depth(int kind);      // tiles a rows workgroup holds (its read-ahead)
+int rows_grid(int key, int kind);
+hipError_t launch_leafrows(int key, int kind, void *data, int64_t row_bytes, const Plan &pl,
                            const Work &w, hipStream_t s);
 
 // Merge sort helpers.

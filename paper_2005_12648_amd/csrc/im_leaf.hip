@@ -734,11 +734,14 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
 // ---- wide rows --------------------------------------------------------------
 // Leaf merge of rows of W bytes ordered by their leading key: the elements of
 // the paper's experiments (Sec. 4), a key followed by a payload.  Rows move
-// in chunks of CH = 16, 8 or 4 bytes (the largest that divides W); a thread
-// holds row_chunks(CH) chunks of a tile (8, 16 or 40), so a tile is R
-// output rows with R * W <= 512 * row_chunks(CH) * CH (64, 64 or 80 KiB:
-// the paper's largest element, a key and 16384 ints = 65540 bytes, moves
-// in 4-byte chunks, one row per tile).  Per tile:
+// in chunks of CH = 16, 8 or 4 bytes; a thread holds CPT chunks of a tile and
+// a workgroup DEPTH tiles in registers, one of the row kinds below:
+//   kind  CH  CPT  DEPTH  tile bytes
+//    0     4   40    2     80 KiB   (the paper's largest element, a key and
+//    1     8   16    2     64 KiB    16384 ints = 65540 bytes, is one row of
+//    2    16    6    3     48 KiB    a kind-0 tile)
+//    3    16    8    2     64 KiB
+// A tile is R output rows with R * W <= 512 * CPT * CH.  Per tile:
 //   1. the keys of its A- and B-slices go to LDS (one load per row);
 //   2. each thread merges four consecutive outputs (stable, ties take A) and
 //      records each output row's input row in LDS;
@@ -746,15 +749,23 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
 //      output order: chunk c of the tile is chunk c of its output window;
 //   4. "inputs read" is published once every load has returned;
 //   5. after the readers of the window have published, a coalesced store.
-// Grid, slot order and reader ranges are those of k_leafmerge at depth 2
-// (slot b, then slots from the counter).  A workgroup
-// holds two tiles in registers, the one waiting to be stored and the next,
-// which it reads before it waits: the depth-2 argument above applies, so a
-// leaf may have 2G tiles.
+// Grid, slot order and reader ranges are those of k_leafmerge (static slots
+// b, b+G, ..., then slots from the counter).  At depth 3 the three register
+// sets hold the tile waiting to be stored, the next one, and the one read
+// before the wait; at depth 2 the first and last.  The read-ahead argument
+// above applies, so a leaf may have DEPTH x G tiles.  The host takes the
+// widest chunk that divides W and the address, and among the two 16-byte
+// kinds the one whose workgroup holds more bytes of whole rows.
+// (Measured on 1 GiB of 64-byte rows: kind 2 holds leaves of 72 MiB against
+// 64 MiB for kind 3, enough to drop a division level; eight chunks per
+// thread at depth 3 spilled registers.)
 constexpr int kRowThreads = 512;
-// chunks per thread and tile, by chunk bytes: two register sets of 32, 32
-// or 40 words
-__host__ __device__ constexpr int row_chunks(int ch) { return ch == 16 ? 8 : (ch == 8 ? 16 : 40); }
+constexpr int kRowKinds = 4;
+__host__ __device__ constexpr int row_ch(int kind) { return kind == 0 ? 4 : (kind == 1 ? 8 : 16); }
+__host__ __device__ constexpr int row_cpt(int kind) {
+    return kind == 0 ? 40 : (kind == 1 ? 16 : (kind == 2 ? 6 : 8));
+}
+__host__ __device__ constexpr int row_depth(int kind) { return kind == 2 ? 3 : 2; }
 constexpr int kRowMaxRows = 2048;
 constexpr int kRowOutsPerThread = kRowMaxRows / kRowThreads;
 
@@ -780,10 +791,11 @@ struct RowGeo {
     int32_t cpr, R, pad;
 };
 
-template <typename K, int CH>
+template <typename K, int KIND>
 struct RowOps {
+    static constexpr int CH = row_ch(KIND);
+    static constexpr int CPT = row_cpt(KIND);
     typedef typename ChunkT<CH>::type C;
-    static constexpr int CPT = row_chunks(CH);
 
     static __device__ __forceinline__ int64_t row_of(const TileGeo &g, int x) {
         return x < g.na ? g.a0 + x : g.b0 + (x - g.na);
@@ -855,23 +867,23 @@ struct RowOps {
     }
 };
 
-template <typename K, int CH>
+template <typename K, int KIND>
 __device__ __forceinline__ bool row_step(unsigned char *data, const RowGeo &rg, const Plan &pl,
                                          const Work &w, K *sk, int64_t *so, int64_t ntiles,
                                          int64_t &t, TileGeo &g, int64_t *s_slot,
                                          unsigned long long &pend, bool &more,
-                                         typename RowOps<K, CH>::C (&cur)[RowOps<K, CH>::CPT],
-                                         typename RowOps<K, CH>::C (&nxt)[RowOps<K, CH>::CPT]) {
+                                         typename RowOps<K, KIND>::C (&cur)[RowOps<K, KIND>::CPT],
+                                         typename RowOps<K, KIND>::C (&nxt)[RowOps<K, KIND>::CPT]) {
     const int64_t tn = hand_over(s_slot, pend, gridDim.x, ntiles, more);
     const bool has = tn < ntiles;
     TileGeo gn = g;
     if (has) {
         gn = tile_geo(w, tn);
-        RowOps<K, CH>::read(data, rg, gn, sk, so, nxt, pl, w);
+        RowOps<K, KIND>::read(data, rg, gn, sk, so, nxt, pl, w);
     }
     const bool ready = wait_window<kRowThreads>(g, pl, w);
     if (threadIdx.x == 0 && has) pend = take_slot(w);
-    if (ready) RowOps<K, CH>::store(data, rg, g, cur);
+    if (ready) RowOps<K, KIND>::store(data, rg, g, cur);
     if (!has) return false;
     more = true;
     t = tn;
@@ -879,10 +891,38 @@ __device__ __forceinline__ bool row_step(unsigned char *data, const RowGeo &rg, 
     return true;
 }
 
-template <typename K, int CH>
+// Depth-3 step: read the slot taken last step into `nxt`, wait for the
+// readers of the oldest tile's window, take the next slot, store the oldest
+// from `cur`; the tile in between stays in the third register set.
+template <typename K, int KIND>
+__device__ __forceinline__ bool row_step3(unsigned char *data, const RowGeo &rg, const Plan &pl,
+                                          const Work &w, K *sk, int64_t *so, int64_t ntiles,
+                                          int64_t first, TileGeo &g, TileGeo &gm, bool &has_m,
+                                          int64_t *s_slot, unsigned long long &pend, bool &took,
+                                          typename RowOps<K, KIND>::C (&cur)[RowOps<K, KIND>::CPT],
+                                          typename RowOps<K, KIND>::C (&nxt)[RowOps<K, KIND>::CPT]) {
+    const int64_t t2 = hand_over(s_slot, pend, first, ntiles, took);
+    const bool has2 = took && t2 < ntiles;
+    TileGeo g2 = gm;
+    if (has2) {
+        g2 = tile_geo(w, t2);
+        RowOps<K, KIND>::read(data, rg, g2, sk, so, nxt, pl, w);
+    }
+    const bool ready = wait_window<kRowThreads>(g, pl, w);
+    if (threadIdx.x == 0 && has2) pend = take_slot(w);
+    took = has2;
+    if (ready) RowOps<K, KIND>::store(data, rg, g, cur);
+    if (!has_m) return false;
+    g = gm;
+    gm = g2;
+    has_m = has2;
+    return true;
+}
+
+template <typename K, int KIND>
 __global__ __launch_bounds__(kRowThreads, 4) void k_leafrows(unsigned char *__restrict__ data,
                                                              RowGeo rg, Plan pl, Work w) {
-    using Ops = RowOps<K, CH>;
+    using Ops = RowOps<K, KIND>;
     __shared__ K sk[kRowMaxRows + 1];
     __shared__ int64_t so[kRowMaxRows];
     int64_t ntiles = (int64_t)w.ctr->tiles;
@@ -894,43 +934,74 @@ __global__ __launch_bounds__(kRowThreads, 4) void k_leafrows(unsigned char *__re
     typename Ops::C ra[Ops::CPT], rb[Ops::CPT];
     TileGeo g = tile_geo(w, t);
     Ops::read(data, rg, g, sk, so, ra, pl, w);
-    bool more = t + gridDim.x < ntiles;
     unsigned long long pend = 0;
-    if (threadIdx.x == 0 && more) pend = take_slot(w);
-    for (;;) {
-        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, s_slot, pend, more, ra, rb)) break;
-        if (!row_step<K, CH>(data, rg, pl, w, sk, so, ntiles, t, g, s_slot, pend, more, rb, ra)) break;
+    if constexpr (row_depth(KIND) == 3) {
+        typename Ops::C rc[Ops::CPT];
+        const int64_t G = gridDim.x;
+        TileGeo gm = g;
+        bool has_m = t + G < ntiles, took = false;
+        if (has_m) {
+            gm = tile_geo(w, t + G);
+            Ops::read(data, rg, gm, sk, so, rb, pl, w);
+            took = true;
+            if (threadIdx.x == 0) pend = take_slot(w);
+        }
+        // the three register sets rotate roles: stored, held, read into
+        for (;;) {
+            if (!row_step3<K, KIND>(data, rg, pl, w, sk, so, ntiles, 2 * G, g, gm, has_m, s_slot,
+                                  pend, took, ra, rc))
+                break;
+            if (!row_step3<K, KIND>(data, rg, pl, w, sk, so, ntiles, 2 * G, g, gm, has_m, s_slot,
+                                  pend, took, rb, ra))
+                break;
+            if (!row_step3<K, KIND>(data, rg, pl, w, sk, so, ntiles, 2 * G, g, gm, has_m, s_slot,
+                                  pend, took, rc, rb))
+                break;
+        }
+    } else {
+        bool more = t + gridDim.x < ntiles;
+        if (threadIdx.x == 0 && more) pend = take_slot(w);
+        for (;;) {
+            if (!row_step<K, KIND>(data, rg, pl, w, sk, so, ntiles, t, g, s_slot, pend, more, ra, rb)) break;
+            if (!row_step<K, KIND>(data, rg, pl, w, sk, so, ntiles, t, g, s_slot, pend, more, rb, ra)) break;
+        }
     }
 }
 
 template <typename K>
-static const void *rows_kernel_ch(int ch) {
-    switch (ch) {
-        case 4: return (const void *)&k_leafrows<K, 4>;
-        case 8: return (const void *)&k_leafrows<K, 8>;
-        case 16: return (const void *)&k_leafrows<K, 16>;
+static const void *rows_kernel_kind(int kind) {
+    switch (kind) {
+        case 0: return (const void *)&k_leafrows<K, 0>;
+        case 1: return (const void *)&k_leafrows<K, 1>;
+        case 2: return (const void *)&k_leafrows<K, 2>;
+        case 3: return (const void *)&k_leafrows<K, 3>;
     }
     return nullptr;
 }
 
-static const void *rows_kernel(int key, int ch) {
+static const void *rows_kernel(int key, int kind) {
     switch (key) {
-        case kI32: return rows_kernel_ch<int32_t>(ch);
-        case kU32: return rows_kernel_ch<uint32_t>(ch);
-        case kI64: return rows_kernel_ch<int64_t>(ch);
-        case kU64: return rows_kernel_ch<uint64_t>(ch);
+        case kI32: return rows_kernel_kind<int32_t>(kind);
+        case kU32: return rows_kernel_kind<uint32_t>(kind);
+        case kI64: return rows_kernel_kind<int64_t>(kind);
+        case kU64: return rows_kernel_kind<uint64_t>(kind);
     }
     return nullptr;
 }
 
-int rows_tile(int64_t row_bytes, int ch) {
-    int64_t r = (int64_t)kRowThreads * row_chunks(ch) * ch / row_bytes;
+int rows_kinds() { return kRowKinds; }
+int rows_chunk_bytes(int kind) { return row_ch(kind); }
+int rows_depth(int kind) { return row_depth(kind); }
+
+int rows_tile(int64_t row_bytes, int kind) {
+    if (kind < 0 || kind >= kRowKinds || row_bytes <= 0) return 0;
+    int64_t r = (int64_t)kRowThreads * row_cpt(kind) * row_ch(kind) / row_bytes;
     if (r > kRowMaxRows) r = kRowMaxRows;
     return r < 1 ? 0 : (int)r;
 }
 
-int rows_grid(int key, int ch) {
-    const void *fn = rows_kernel(key, ch);
+int rows_grid(int key, int kind) {
+    const void *fn = rows_kernel(key, kind);
     if (!fn) return 0;
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -941,11 +1012,13 @@ int rows_grid(int key, int ch) {
     return per_cu < 1 ? 0 : per_cu * cus;
 }
 
-hipError_t launch_leafrows(int key, int ch, void *data, int64_t row_bytes, const Plan &pl,
+hipError_t launch_leafrows(int key, int kind, void *data, int64_t row_bytes, const Plan &pl,
                            const Work &w, hipStream_t s) {
-    const void *fn = rows_kernel(key, ch);
-    const int R = rows_tile(row_bytes, ch);
-    if (!fn || R < 1 || row_bytes % ch != 0 || pl.tile != R) return hipErrorInvalidValue;
+    const void *fn = rows_kernel(key, kind);
+    const int R = rows_tile(row_bytes, kind);
+    if (!fn || R < 1 || pl.tile != R) return hipErrorInvalidValue;
+    const int ch = row_ch(kind);
+    if (row_bytes % ch != 0) return hipErrorInvalidValue;
     RowGeo rg;
     rg.W = row_bytes;
     rg.cpr = (int32_t)(row_bytes / ch);

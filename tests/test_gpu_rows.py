@@ -63,10 +63,13 @@ def run(rows, la, dev):
     return bad, st
 
 
-# (row bytes, rows in A, rows in B): chunk 16 / 8 / 4 bytes, ragged tiles
+# (row bytes, rows in A, rows in B): chunk 16 / 8 / 4 bytes, ragged tiles;
+# 16-byte rows of up to 16 KiB take the three-deep kind, 32 and 64 KiB ones
+# the two-deep kind with larger tiles
 SHAPES = [(4, 70001, 65537), (8, 40000, 50003), (12, 30001, 29999), (16, 25000, 27001),
           (20, 20011, 19999), (64, 9001, 12007), (100, 5003, 4001), (256, 3001, 2999),
-          (1000, 1201, 999), (4096, 301, 277), (16384, 77, 91), (65536, 23, 19),
+          (1000, 1201, 999), (4096, 301, 277), (16384, 77, 91), (32768, 31, 29),
+          (65536, 23, 19),
           # the paper's largest element (key + 16384 ints); 8-byte multiples
           # above 32 KiB; above 64 KiB in 4-byte chunks
           (65540, 23, 19), (32776, 40, 33), (81920, 17, 21)]
