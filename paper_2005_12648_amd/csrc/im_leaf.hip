@@ -840,15 +840,16 @@ struct RowOps {
                                                 const TileGeo &g, K *sk, int64_t *so,
                                                 C (&r)[CPT], const Plan &pl, const Work &w) {
         order(data, rg, g, sk, so);
-        const int nch = g.n * rg.cpr;
+        // Branch-free gather: a lane past the tile's last chunk reloads that
+        // chunk (its store is dropped by the store descriptor's range), so
+        // every load of the tile is in flight at once.
+        const int last = g.n * rg.cpr - 1;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            const int c = (int)threadIdx.x + q * kRowThreads;
-            if (c < nch) {
-                const int o = rg.cpr == 1 ? c : (int)__umulhi((uint32_t)c, rg.magic);
-                const int part = c - o * rg.cpr;
-                r[q] = *reinterpret_cast<const C *>(data + so[o] + part * CH);
-            }
+            const int c = min((int)threadIdx.x + q * kRowThreads, last);
+            const int o = rg.cpr == 1 ? c : (int)__umulhi((uint32_t)c, rg.magic);
+            const int part = c - o * rg.cpr;
+            r[q] = *reinterpret_cast<const C *>(data + so[o] + part * CH);
         }
         wait_dma();
         __syncthreads();
@@ -860,10 +861,8 @@ struct RowOps {
         const int nch = g.n * rg.cpr;
         const __amdgpu_buffer_rsrc_t ro = buf_rsrc(data + g.out0 * rg.W, (int64_t)nch * CH);
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int c = (int)threadIdx.x + q * kRowThreads;
-            if (c < nch) chunk_store<CH>(r[q], ro, c * CH);
-        }
+        for (int q = 0; q < CPT; ++q)   // (offsets past nch * CH are dropped)
+            chunk_store<CH>(r[q], ro, ((int)threadIdx.x + q * kRowThreads) * CH);
     }
 };
 
