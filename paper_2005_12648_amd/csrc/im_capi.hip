@@ -1293,6 +1293,7 @@ int batched_inplace_merge_graph(im_graph **out, void *data, const int64_t *d_off
             return fail(IM_ERR_HIP, "could not size the leaf merge grid");
         ensure_err_word(ds);
     }
+    set_cells(pl, n == 1);   // a single pair is tiled by output cells, as in the eager call
     if (pl.leaf_shift == 0)
         return fail(IM_ERR_INVALID_ARG, "too many instances for the 64-bit leaf/tile counter");
     pl.epoch = 1;   // every replay clears the flags first

@@ -179,6 +179,43 @@ def test_graph_single_instance_division(dev, leaf_tiles):
         g.close()
 
 
+@pytest.mark.parametrize("tiles", [None, 4])
+def test_graph_single_pair_cells(dev, leaf_tiles, tiles):
+    # one pair in a graph is tiled by cells of the whole output, as in the
+    # eager call (four-tile leaves: several division levels); replays with
+    # new keys, then offsets that move the pair, shrink it, leave it in
+    # order, or put all of B first
+    leaf_tiles(tiles)
+    la, lb = 700001, 650003
+    total = la + lb
+    base = gen.pair_uniform(la, lb, 91)
+    buf = d(base, dev)
+    offs = d(np.array([0, la, total], dtype=np.int64), dev)
+    g = im.MergeGraph(buf, offs)
+    try:
+        cases = [(0, la, lb, "uniform"), (0, la, lb, "uniform"), (7, 400000, 900000, "uniform"),
+                 (0, 3, total - 3, "uniform"), (0, la, lb, "ordered"), (11, 500000, 500000, "inverted")]
+        for r, (o0, a, b, kind) in enumerate(cases):
+            x = np.random.default_rng(300 + r).integers(0, 2 ** 31, size=total).astype(np.int32)
+            pair = gen.pair_uniform(a, b, 310 + r)
+            if kind == "ordered":
+                pair = np.sort(pair)
+            elif kind == "inverted":
+                pair = np.concatenate([np.sort(pair)[b:], np.sort(pair)[:b]])
+                a, b = pair.size - b, b
+            x[o0:o0 + a + b] = pair
+            offs.copy_(d(np.array([o0, o0 + a, o0 + a + b], dtype=np.int64), dev))
+            buf.copy_(d(x, dev))
+            say("single-pair graph replay", r, o0, a, b, kind)
+            g.launch()
+            torch.cuda.synchronize()
+            want = x.copy()
+            want[o0:o0 + a + b] = oracle.merge(pair, a)
+            assert np.array_equal(h(buf), want), r
+    finally:
+        g.close()
+
+
 # ----------------------------------------------------------------- autotune
 def test_autotune_choice_is_used(dev):
     data, off = gen.batch(128, 81, lo_exp=2.0, hi_exp=14.0)
