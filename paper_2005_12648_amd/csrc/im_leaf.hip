@@ -739,7 +739,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
 //   kind  CH  CPT  DEPTH  tile bytes
 //    0     4   40    2     80 KiB   (the paper's largest element, a key and
 //    1     8   16    2     64 KiB    16384 ints = 65540 bytes, is one row of
-//    2    16    6    3     48 KiB    a kind-0 tile)
+//    2    16    7    3     56 KiB    a kind-0 tile)
 //    3    16    8    2     64 KiB
 // A tile is R output rows with R * W <= 512 * CPT * CH.  Per tile:
 //   1. the keys of its A- and B-slices go to LDS (one load per row);
@@ -756,14 +756,15 @@ __global__ __launch_bounds__(THREADS, 4) void k_smallmerge(K *__restrict__ keys,
 // above applies, so a leaf may have DEPTH x G tiles.  The host takes the
 // widest chunk that divides W and the address, and among the two 16-byte
 // kinds the one whose workgroup holds more bytes of whole rows.
-// (Measured on 1 GiB of 64-byte rows: kind 2 holds leaves of 72 MiB against
-// 64 MiB for kind 3, enough to drop a division level; eight chunks per
-// thread at depth 3 spilled registers.)
+// (Measured on 1 GiB of 64-byte rows: a node of 128 MiB is a leaf for kind 2
+// and not for kind 3, so kind 3 would need a fourth division level; seven
+// chunks per thread beat six by 4-8% in the leaf stage; eight at depth 3
+// spilled registers.)
 constexpr int kRowThreads = 512;
 constexpr int kRowKinds = 4;
 __host__ __device__ constexpr int row_ch(int kind) { return kind == 0 ? 4 : (kind == 1 ? 8 : 16); }
 __host__ __device__ constexpr int row_cpt(int kind) {
-    return kind == 0 ? 40 : (kind == 1 ? 16 : (kind == 2 ? 6 : 8));
+    return kind == 0 ? 40 : (kind == 1 ? 16 : (kind == 2 ? 7 : 8));
 }
 __host__ __device__ constexpr int row_depth(int kind) { return kind == 2 ? 3 : 2; }
 constexpr int kRowMaxRows = 2048;

@@ -87,6 +87,27 @@ def test_rows_shapes(dev, env, row_bytes, la, lb):
     assert st["leaf_elems"] + st["rotated_elems"] > 0
 
 
+@pytest.mark.parametrize("shift_words", [1, 2])
+@pytest.mark.parametrize("row_bytes,la,lb", [(48, 20011, 19999), (64, 9001, 12007),
+                                             (1024, 1201, 999)])
+def test_rows_unaligned_base(dev, env, shift_words, row_bytes, la, lb):
+    # rows whose base lies 4 or 8 bytes past a 16-byte boundary move in the
+    # widest chunk the address allows (the 4- and 8-byte row kinds), with
+    # several division levels; nothing before the base is written
+    env(tiles=3)
+    rows = gen.rows_pair(la, lb, row_bytes // 4, 500 + row_bytes + shift_words)
+    n, words = rows.shape
+    buf = torch.zeros(n * words + shift_words, dtype=torch.int32, device=dev)
+    t = buf[shift_words:].view(n, words)
+    assert t.data_ptr() % 16 == 4 * shift_words
+    t.copy_(d(rows, dev))
+    say("rows unaligned", row_bytes, la, lb, shift_words)
+    im.inplace_merge_rows(t, la)
+    bad = np.flatnonzero(np.any(h(t) != oracle.merge_rows(rows, la), axis=1))
+    assert bad.size == 0, "%d rows differ, first %d" % (bad.size, bad[0])
+    assert np.all(h(buf[:shift_words]) == 0)
+
+
 def test_rows_too_wide_refused(dev):
     rows = np.zeros((4, 81924 // 4), dtype=np.int32)
     t = d(rows, dev)
