@@ -296,14 +296,14 @@ struct LeafOps {
         }
         __syncthreads();                     // LDS inputs of this tile are dead
         // blocked -> striped: IPT is odd, so the blocked writes (stride IPT
-        // words) hit distinct banks.
+        // words) hit distinct banks.  No test against n: every position is
+        // below THREADS * IPT, inside the tile's LDS, and outputs past n are
+        // never stored (no branch per output, which costs registers).
         const int x0 = tid * IPT;
 #pragma unroll
         for (int e = 0; e < IPT; ++e) {
-            if (x0 + e < n) {
-                sk[x0 + e] = out[e];
-                if constexpr (HAS_V) sv[x0 + e] = vout[e];
-            }
+            sk[x0 + e] = out[e];
+            if constexpr (HAS_V) sv[x0 + e] = vout[e];
         }
         __syncthreads();
         int xb = tid;
@@ -329,18 +329,12 @@ struct LeafOps {
                 out[4 * u + 3] = __builtin_bit_cast(K, w3);
             }
 #pragma unroll
-            for (int r = 0; r < VR; ++r) {
-                const int x = VQ * 4 * THREADS + xb + r * THREADS;
-                if (x < n) out[4 * VQ + r] = sk[x];
-            }
+            for (int r = 0; r < VR; ++r) out[4 * VQ + r] = sk[VQ * 4 * THREADS + xb + r * THREADS];
         } else {
 #pragma unroll
             for (int u = 0; u < IPT; ++u) {
-                const int x = xb + u * THREADS;
-                if (x < n) {
-                    out[u] = sk[x];
-                    if constexpr (HAS_V) vout[u] = sv[x];
-                }
+                out[u] = sk[xb + u * THREADS];
+                if constexpr (HAS_V) vout[u] = sv[xb + u * THREADS];
             }
         }
         before_last_sync();
@@ -391,19 +385,16 @@ struct LeafOps {
             }
             return;
         }
+        // (outputs past n fall outside the descriptors' ranges: dropped)
 #pragma unroll
-        for (int u = 0; u < IPT; ++u) {
-            const int x = xb + u * THREADS;
-            if (x < n) buf_store<K>(out[u], ro, x * (int)sizeof(K));
-        }
+        for (int u = 0; u < IPT; ++u)
+            buf_store<K>(out[u], ro, (xb + u * THREADS) * (int)sizeof(K));
         if constexpr (HAS_V) {
             const __amdgpu_buffer_rsrc_t rv =
                 buf_rsrc(vals + g.out0, (int64_t)n * sizeof(V));
 #pragma unroll
-            for (int u = 0; u < IPT; ++u) {
-                const int x = xb + u * THREADS;
-                if (x < n) buf_store<V>(vout[u], rv, x * (int)sizeof(V));
-            }
+            for (int u = 0; u < IPT; ++u)
+                buf_store<V>(vout[u], rv, (xb + u * THREADS) * (int)sizeof(V));
         }
     }
 };
