@@ -123,12 +123,23 @@ __device__ __forceinline__ void stage_tile_dma(const E *__restrict__ base_ptr, c
     asm volatile("" : "+v"(xb));
     const int wbase = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
     const int naw = g.na * D, nw = g.n * D;
+    // A whole tile (every tile of a leaf but its last) loads every slot: one
+    // uniform test for the tile instead of an exec mask around each load.
+    if (nw == THREADS * IPT * D) {
 #pragma unroll
-    for (int u = 0; u < IPT * D; ++u) {
-        const int j = xb + u * THREADS;
-        if (j < nw) {
+        for (int u = 0; u < IPT * D; ++u) {
+            const int j = xb + u * THREADS;
             const uint32_t *src = j < naw ? A + j : B + (j - naw);
             __builtin_amdgcn_global_load_lds(src, S + wbase + u * THREADS, 4, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < IPT * D; ++u) {
+            const int j = xb + u * THREADS;
+            if (j < nw) {
+                const uint32_t *src = j < naw ? A + j : B + (j - naw);
+                __builtin_amdgcn_global_load_lds(src, S + wbase + u * THREADS, 4, 0, 0);
+            }
         }
     }
 }
