@@ -845,14 +845,17 @@ struct RowOps {
         order(data, rg, g, sk, so);
         // Branch-free gather: a lane past the tile's last chunk reloads that
         // chunk (its store is dropped by the store descriptor's range), so
-        // every load of the tile is in flight at once.
+        // every load of the tile is in flight at once.  (A tile always has a
+        // row; the uniform test only keeps an empty one from reading so[].)
         const int last = g.n * rg.cpr - 1;
+        if (last >= 0) {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int c = min((int)threadIdx.x + q * kRowThreads, last);
-            const int o = rg.cpr == 1 ? c : (int)__umulhi((uint32_t)c, rg.magic);
-            const int part = c - o * rg.cpr;
-            r[q] = *reinterpret_cast<const C *>(data + so[o] + part * CH);
+            for (int q = 0; q < CPT; ++q) {
+                const int c = min((int)threadIdx.x + q * kRowThreads, last);
+                const int o = rg.cpr == 1 ? c : (int)__umulhi((uint32_t)c, rg.magic);
+                const int part = c - o * rg.cpr;
+                r[q] = *reinterpret_cast<const C *>(data + so[o] + part * CH);
+            }
         }
         wait_dma();
         __syncthreads();
