@@ -14,7 +14,9 @@ No GPU.  The oracle (``oracle/``) is checked against:
     input, B|A on inverted input (the early exits of Alg. 1 and Alg. 2/3);
   * co-rank properties: i(0) = 0, i(N) = L_A, steps of 0 or 1;
   * the network's gradients against central finite differences, and the
-    first Adam step against its closed form.
+    first Adam step against its closed form;
+  * the merge-sort result against a bottom-up merge sort built from the
+    oracle's own merge.
 """
 import itertools
 import math
@@ -367,3 +369,28 @@ def test_merge_rows_brute(dt):
     x = np.array([[3], [7], [1], [9]], dtype=dt)
     assert np.array_equal(oracle.merge_rows(x, 2)[:, 0], oracle.merge(x[:, 0].copy(), 2))
     assert x[:, 0].tolist() == [3, 7, 1, 9]
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.int64])
+def test_sort_keys_equals_bottom_up_merges(dt):
+    # the merge-sort driver's result (the sorted input) equals a bottom-up
+    # merge sort built from the oracle's own stable merge: runs of width w
+    # merged pairwise, the unpaired last run carried over, w doubling (the
+    # passes of the library's sort, Q17), so each pins the other; also
+    # sortedness and the same multiset
+    rng = np.random.default_rng(23)
+    for n in (0, 1, 2, 3, 7, 64, 1000, 4099):
+        for hi in (4, 2 ** 31):
+            x = rng.integers(0, hi, n).astype(dt)
+            y = x.copy()
+            w = 1
+            while w < n:
+                for o in range(0, n, 2 * w):
+                    e = min(o + 2 * w, n)
+                    if o + w < e:
+                        y[o:e] = oracle.merge(y[o:e].copy(), w)
+                w *= 2
+            s = oracle.sort_keys(x)
+            assert np.array_equal(s, y), (n, hi)
+            assert np.all(s[1:] >= s[:-1])
+            assert sorted(s.tolist()) == sorted(x.tolist())
