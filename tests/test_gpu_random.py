@@ -51,7 +51,7 @@ def lengths(r):
     return one(), one()
 
 
-@pytest.mark.parametrize("case", range(160))
+@pytest.mark.parametrize("case", range(1000))
 def test_random_case(dev, knobs, case):
     r = np.random.default_rng(20051264 + case)
     tiles = [None, 2, 3, 7][r.integers(4)]
