@@ -69,6 +69,9 @@ def run(rows, la, dev):
 SHAPES = [(4, 70001, 65537), (8, 40000, 50003), (12, 30001, 29999), (16, 25000, 27001),
           (20, 20011, 19999), (64, 9001, 12007), (100, 5003, 4001), (256, 3001, 2999),
           (1000, 1201, 999), (4096, 301, 277), (16384, 77, 91), (32768, 31, 29),
+          # the largest row of a three-deep tile (56 KiB) and the next 16-byte
+          # multiple, which takes the two-deep kind
+          (57344, 9, 11), (57360, 10, 9),
           (65536, 23, 19),
           # the paper's largest element (key + 16384 ints); 8-byte multiples
           # above 32 KiB; above 64 KiB in 4-byte chunks
