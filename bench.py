@@ -630,10 +630,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--forms", choices=["all", "none", "rows", "learned", "exchanges", "c1"],
+    ap.add_argument("--forms", choices=["all", "none", "rows", "learned", "exchanges", "c1", "sort"],
                     default="all",
                     help="other workloads after the headline: all, none, or only the rows, "
-                         "the learned-split, the exchange or the small (c1) forms")
+                         "the learned-split, the exchange, the small (c1) or the merge-sort forms")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (profiling runs: default leaf configuration)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -703,6 +703,8 @@ def main():
         forms["c1"] = bench_variant(torch, im, oracle, gen, dev, "c1", 3)
     elif args.forms == "exchanges":
         forms["f3_exchange_and_out_of_place"] = bench_exchanges(torch, im, oracle, gen, dev, 3)
+    elif args.forms == "sort":
+        forms["c4_sort"] = bench_sort(torch, im, oracle, gen, dev)
     st = head["stats"]
     line = {
         "metric": "Gelem/s, in-place merge of int32 L_A=L_B=2^27",
