@@ -846,8 +846,6 @@ int inplace_merge_kv(void *keys, void *vals, int64_t L_A, int64_t L_B, int key_d
                         L_A + L_B, L_A, L_B, nullptr, stream);
 }
 
-// Rows: the largest chunk (16, 8 or 4 bytes) that divides the row and the
-// data address; 0 if the row shape is not supported.
 // Row kind of a rows merge, -1 (with *why) if the rows cannot be merged:
 // the widest chunk that divides the row and the address and still puts a
 // whole row in a tile; of the 16-byte kinds, the one whose workgroup holds
